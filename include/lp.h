@@ -1,0 +1,163 @@
+/*
+ * lp.h -- C ABI of the MI355X (gfx950) FFT evaluation of artificial
+ * night-sky-brightness maps.
+ *
+ * Method (Bara, Falchi, Furgoni, Lima 2019, "Fast Fourier-transform
+ * calculation of artificial night sky brightness maps"):
+ *   - for factorable sources (Sec. 2.2, Eq. 3) and a shift-invariant
+ *     point-spread function (Sec. 2.3), the sky-brightness map B is the 2-D
+ *     convolution of the ground radiance L1 with the kernel K (Eq. 7);
+ *   - it is evaluated through the convolution theorem (Eq. 9) with the 2-D
+ *     DFT of Eq. 10, after zero padding both matrices to at least
+ *     N_L + N_K - 1 rows and columns so the circular convolution equals the
+ *     linear one (Sec. 2.5, Fig. 1);
+ *   - the output map has the input's size (Sec. 3).
+ *
+ * Discrete statement computed here, for a radiance grid R (ny x nx) and a
+ * kernel K (ky x kx) with centre (cy, cx) = ((ky-1)/2, (kx-1)/2):
+ *     S(i,j) = sum_{a<ky, b<kx} K(a,b) R(i+cy-a, j+cx-b),  0<=i<ny, 0<=j<nx,
+ * with R = 0 outside the grid.  K(a,b) is the kernel at observer-minus-source
+ * displacement ((a-cy) pitch, (b-cx) pitch).  No area element is applied (the
+ * caller folds pitch^2 into K if wanted).
+ *
+ * Conventions for every call:
+ *   - arrays are row-major and dense;
+ *   - "device" pointers are HIP device memory on the current device, owned by
+ *     the caller; "host" pointers are ordinary host memory owned by the
+ *     caller;
+ *   - calls that take device data enqueue work on the stream given to
+ *     lp_plan_bind / lp_batch_bind and return without synchronising; errors
+ *     in that work surface at the caller's next synchronisation;
+ *   - a plan (or batch) is not safe for concurrent use from several host
+ *     threads; use one per stream;
+ *   - on failure a call returns a negative lp_status (or NULL) and
+ *     lp_last_error() describes it; argument checks happen before any HIP
+ *     call, so a rejected call has no device side effects.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_plan lp_plan;   /* opaque: one map shape + one kernel */
+typedef struct lp_batch lp_batch; /* opaque: many tiles, several kernels */
+
+typedef enum lp_status {
+    LP_OK = 0,
+    LP_E_INVALID = -1, /* size <= 0, null pointer, bad pitch, non-finite kernel */
+    LP_E_SIZE = -2,    /* padding too small, not 5-smooth, or beyond the maximum */
+    LP_E_STATE = -3,   /* call out of order (e.g. convolve before spectrum)      */
+    LP_E_NOMEM = -4,   /* workspace unbound or too small                         */
+    LP_E_DEVICE = -5   /* a HIP runtime or launch error                          */
+} lp_status;
+
+/* Spectrum storage forms (lp_plan_spectrum_form). */
+enum { LP_FORM_NONE = 0, LP_FORM_REAL_QUADRANT = 1, LP_FORM_COMPLEX = 2 };
+
+/* Largest padded sizes a plan accepts: a padded column of Py complex FP32
+ * values, and half a padded row plus one, must each fit one workgroup's LDS. */
+#define LP_MAX_PY 20480
+#define LP_MAX_PX 40958
+
+/* Text description of the last failure on this host thread ("" if none).
+ * The pointer stays valid until the next lp_* call on the same thread. */
+const char *lp_last_error(void);
+
+/* lp_status of the last failure on this host thread (LP_OK if the last call
+ * succeeded); lets a caller classify a NULL from lp_plan_create. */
+int lp_last_status(void);
+
+/* Library version string. */
+const char *lp_version(void);
+
+/* ---------------------------------------------------------------- plans --
+ * lp_plan_create: a plan for maps of ny x nx pixels and kernels of ky x kx
+ * pixels on a grid of pitch_km (Eq. 7, Sec. 2.5).  Host only; no HIP call.
+ * The padded size defaults, per axis, to the smallest number 2^a 3^b 5^c that
+ * is >= n + k - 1 (the common size of Sec. 2.5), and even along x.
+ * Returns NULL on error (sizes <= 0, pitch <= 0 or non-finite: LP_E_INVALID;
+ * default padding above LP_MAX_PY / LP_MAX_PX: LP_E_SIZE). */
+lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double pitch_km);
+
+/* Free the plan (host memory only; the bound workspace stays the caller's).
+ * NULL is accepted. */
+void lp_plan_destroy(lp_plan *plan);
+
+/* Override the padded size (Sec. 2.5 allows any size >= n + k - 1; the result
+ * does not depend on it beyond round-off).  py >= ny+ky-1 and px >= nx+kx-1,
+ * both 5-smooth, px even, py <= LP_MAX_PY, px <= LP_MAX_PX (else LP_E_SIZE).
+ * Must precede lp_plan_bind (else LP_E_STATE). */
+int lp_plan_set_padding(lp_plan *plan, int64_t py, int64_t px);
+
+/* Current padded size into *py, *px (host pointers). */
+int lp_plan_get_padding(const lp_plan *plan, int64_t *py, int64_t *px);
+
+/* Device workspace the plan needs, in bytes (0 for a NULL plan): the
+ * intermediate spectra of the map, the stored kernel spectrum and the FP32
+ * twiddle tables.  Depends on the padding. */
+size_t lp_plan_workspace_bytes(const lp_plan *plan);
+
+/* Attach caller-owned device memory (dev_ws, >= lp_plan_workspace_bytes,
+ * 256-byte aligned) and a stream (a hipStream_t; NULL = the null stream).
+ * Uploads the twiddle tables (async on that stream).  May be called again to
+ * move the plan to another workspace or stream; the kernel spectrum must then
+ * be computed again.  LP_E_NOMEM if bytes is too small. */
+int lp_plan_bind(lp_plan *plan, void *dev_ws, size_t bytes, void *stream);
+
+/* Kernel spectrum (Fig. 1 "FFT(K)", Eq. 9, Eq. 10): K is placed wrap-centred
+ * in the Py x Px padded grid, transformed by a direct FP64 DFT on the device,
+ * scaled by 1/(Py Px), rounded once to FP32 and kept in the workspace.  If K
+ * is exactly mirror-symmetric on both axes with odd sizes, its spectrum is
+ * real and even and only one real quadrant is stored; otherwise the complex
+ * Hermitian half.  psf: host, FP64, ky*kx row-major, read during the call
+ * only.  Synchronises the bound stream before returning.  Errors:
+ * LP_E_INVALID (null, NaN or Inf entries), LP_E_STATE (not bound). */
+int lp_kernel_spectrum(lp_plan *plan, const double *psf);
+
+/* Which spectrum form the plan holds (LP_FORM_*). */
+int lp_plan_spectrum_form(const lp_plan *plan);
+
+/* Copy the stored spectrum to host memory in natural order as FP32 complex
+ * pairs, out[(u * (Px/2+1) + v) * 2 + {0: re, 1: im}] for 0<=u<Py,
+ * 0<=v<=Px/2, already scaled by 1/(Py Px).  Synchronises the bound stream.
+ * out must hold Py*(Px/2+1)*2 floats. */
+int lp_plan_read_spectrum(lp_plan *plan, float *out);
+
+/* The hot path: S = K (*) R cropped to ny x nx (Eq. 7 via Eq. 9).
+ * radiance: device FP32 ny*nx; out: device FP32 ny*nx (may alias radiance).
+ * Three kernels on the bound stream: rows forward real-to-complex transform
+ * with implicit zero padding; per-column forward transform, multiply by the
+ * kernel spectrum, inverse transform; rows inverse complex-to-real transform
+ * with the crop.  Non-finite radiance is not checked (one NaN spreads over
+ * the whole map through the transform).  Errors: LP_E_INVALID (null),
+ * LP_E_STATE (no spectrum), LP_E_NOMEM (unbound), LP_E_DEVICE. */
+int lp_convolve(lp_plan *plan, const float *radiance, float *out);
+
+/* Transpose of lp_convolve (correlation with K: the same kernels with the
+ * conjugate spectrum), for gradients: grad_in = C^T grad_out.  Device FP32
+ * ny*nx in and out (may alias).  Same errors as lp_convolve. */
+int lp_adjoint(lp_plan *plan, const float *grad_out, float *grad_in);
+
+/* Per-stage timing with HIP events on the bound stream.  enable != 0 starts
+ * recording events around each of the three stages of every lp_convolve /
+ * lp_adjoint call (up to 1024 calls are kept); lp_plan_stage_ms synchronises
+ * on the last event, writes the summed milliseconds of stage s (0: rows
+ * forward, 1: columns, 2: rows inverse) to ms[s] for s < n, the number of
+ * calls to *calls, and clears the record. */
+int lp_plan_timing(lp_plan *plan, int enable);
+int lp_plan_stage_ms(lp_plan *plan, double *ms, int n, int *calls);
+
+/* Launch shape the plan chose (host pointers, any may be NULL): columns per
+ * workgroup of the column stage, rows per workgroup of the row stages. */
+int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

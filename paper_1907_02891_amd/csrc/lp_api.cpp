@@ -1,0 +1,572 @@
+// Host side of the C ABI (include/lp.h): plans, workspace layout, twiddle
+// tables, the kernel spectrum and the launch sequence of the hot path.
+#include "lp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int g_status = LP_OK;
+
+void clear_error()
+{
+    g_err.clear();
+    g_status = LP_OK;
+}
+
+int fail(int code, const char *fmt, ...)
+{
+    g_status = code;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(LP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_5smooth(int64_t n)
+{
+    if (n <= 0) return false;
+    for (int f : {2, 3, 5})
+        while (n % f == 0) n /= f;
+    return n == 1;
+}
+
+int64_t next_5smooth(int64_t n, bool even)
+{
+    for (int64_t m = std::max<int64_t>(n, 1);; ++m)
+        if (is_5smooth(m) && (!even || m % 2 == 0)) return m;
+}
+
+// cos and sin of 2 pi m / n, with m reduced exactly modulo n and the angle
+// folded into [0, pi/4] by octant symmetry before the FP64 evaluation, so
+// that e.g. quarter turns give exact zeros.
+void exp_frac(int64_t m, int64_t n, double *c, double *s)
+{
+    m %= n;
+    if (m < 0) m += n;
+    const int64_t m8 = 8 * m;
+    const int64_t o = m8 / n;  // octant 0..7
+    const long double pi4 = 0.785398163397448309615660845819875721L;
+    long double phi;
+    if (o % 2 == 0)
+        phi = pi4 * static_cast<long double>(m8 - o * n) / static_cast<long double>(n);
+    else
+        phi = pi4 * static_cast<long double>((o + 1) * n - m8) / static_cast<long double>(n);
+    const double cp = static_cast<double>(cosl(phi)), sp = static_cast<double>(sinl(phi));
+    switch (o) {
+        case 0: *c = cp; *s = sp; break;
+        case 1: *c = sp; *s = cp; break;
+        case 2: *c = -sp; *s = cp; break;
+        case 3: *c = -cp; *s = sp; break;
+        case 4: *c = -cp; *s = -sp; break;
+        case 5: *c = -sp; *s = -cp; break;
+        case 6: *c = sp; *s = -cp; break;
+        default: *c = cp; *s = -sp; break;
+    }
+}
+
+// Radix sequence for a 5-smooth length: as many 8s as possible (a trailing
+// 2^1 or 2^2 becomes 4 or 4*4 / 2), then 5s, then 3s.
+std::vector<int> radices(int64_t n)
+{
+    int a = 0, b = 0, c = 0;
+    while (n % 2 == 0) { n /= 2; ++a; }
+    while (n % 3 == 0) { n /= 3; ++b; }
+    while (n % 5 == 0) { n /= 5; ++c; }
+    std::vector<int> r;
+    int e8 = a / 3, rem = a % 3;
+    if (rem == 1 && e8 > 0) { --e8; rem = 4; }  // 8*2 -> 4*4
+    for (int i = 0; i < e8; ++i) r.push_back(8);
+    if (rem == 2) r.push_back(4);
+    else if (rem == 4) { r.push_back(4); r.push_back(4); }
+    for (int i = 0; i < c; ++i) r.push_back(5);
+    for (int i = 0; i < b; ++i) r.push_back(3);
+    if (rem == 1) r.push_back(2);
+    return r;
+}
+
+// Pass list and FP32 twiddle table (FP64 values rounded once) of a length-n
+// Stockham transform.  The table has n - 1 entries (sum of p * (r - 1)).
+void make_fft(int64_t n, lp::FftDesc *d, std::vector<float> *tw)
+{
+    std::memset(d, 0, sizeof *d);
+    d->n = static_cast<int32_t>(n);
+    std::vector<int> rs = radices(n);
+    tw->clear();
+    int64_t p = 1;
+    for (size_t i = 0; i < rs.size(); ++i) {
+        lp::FftPass &P = d->pass[i];
+        const int r = rs[i];
+        P.radix = r;
+        P.p = static_cast<int32_t>(p);
+        P.nb = static_cast<int32_t>(n / r);
+        P.tw = static_cast<int32_t>(tw->size() / 2);
+        P.inv_p = 1.0f / static_cast<float>(p);
+        for (int64_t k = 0; k < p; ++k)
+            for (int j = 1; j < r; ++j) {
+                double c, s;
+                exp_frac(j * k, p * r, &c, &s);
+                tw->push_back(static_cast<float>(c));
+                tw->push_back(static_cast<float>(-s));
+            }
+        p *= r;
+    }
+    d->npass = static_cast<int32_t>(rs.size());
+    if (tw->empty()) { tw->push_back(1.f); tw->push_back(0.f); }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+int ilog2(int64_t v)
+{
+    int l = 0;
+    while ((int64_t{1} << (l + 1)) <= v) ++l;
+    return l;
+}
+
+int threads_for(int64_t elems)
+{
+    int64_t t = (elems + 7) / 8;
+    t = ((t + 63) / 64) * 64;
+    return static_cast<int>(std::min<int64_t>(1024, std::max<int64_t>(64, t)));
+}
+
+}  // namespace
+
+struct lp_plan {
+    int64_t ny, nx, ky, kx;
+    double pitch;
+    int64_t py, px, m, h;
+    // launch shape
+    int logc, logb;
+    int64_t nblk;
+    int t_rows, t_cols;
+    // transforms and tables (host copies)
+    lp::FftDesc fx, fy;
+    std::vector<float> twx, twy, rtw;
+    // workspace layout (byte offsets)
+    size_t off_w, off_kh, off_twx, off_twy, off_rtw, bytes;
+    size_t scratch_bytes;
+    // binding
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    int form = LP_FORM_NONE;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int ev_calls = 0;
+};
+
+namespace {
+
+constexpr int kMaxTimedCalls = 1024;
+
+void layout(lp_plan *p)
+{
+    const int64_t C = int64_t{1} << p->logc;
+    const size_t w = static_cast<size_t>(p->nblk) * p->ny * C * 8;
+    const size_t scratch = align256(p->ky * p->kx * 8) + align256(p->ky * p->h * 16) +
+                           align256(p->px * 16) + align256(p->py * 16);
+    p->scratch_bytes = scratch;
+    p->off_w = 0;
+    p->off_kh = align256(std::max(w, scratch));
+    p->off_twx = p->off_kh + align256(static_cast<size_t>(p->nblk) * p->py * C * 8);
+    p->off_rtw = p->off_twx + align256(p->twx.size() * 4);
+    p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
+    p->bytes = p->off_twy + align256(p->twy.size() * 4);
+}
+
+// Launch shape: C = columns per workgroup of the column stage (a power of
+// two whose Py*C complex values fit LDS, keeping >= min(H, 512) workgroups);
+// B = rows per workgroup of the row stages ((M+1)*B complex in LDS, B*C <= 32,
+// >= min(ny, 256) workgroups).
+void choose_shape(lp_plan *p)
+{
+    int logc = 0;
+    for (int l = 6; l >= 0; --l) {
+        const int64_t C = int64_t{1} << l;
+        const int64_t nblk = (p->h + C - 1) / C;
+        if (p->py * C * 8 <= lp::kLdsBytes && nblk >= std::min<int64_t>(p->h, 512)) { logc = l; break; }
+    }
+    p->logc = logc;
+    p->nblk = (p->h + (int64_t{1} << logc) - 1) >> logc;
+    int logb = 0;
+    for (int l = 5; l >= 0; --l) {
+        const int64_t B = int64_t{1} << l;
+        const int64_t groups = (p->ny + B - 1) / B;
+        if ((p->m + 1) * B * 8 <= lp::kLdsBytes && (B << logc) <= 32 &&
+            groups >= std::min<int64_t>(p->ny, 256)) { logb = l; break; }
+    }
+    p->logb = logb;
+    p->t_cols = threads_for(p->py << logc);
+    p->t_rows = threads_for(p->m << logb);
+}
+
+int set_padding(lp_plan *p, int64_t py, int64_t px)
+{
+    if (py < p->ny + p->ky - 1 || px < p->nx + p->kx - 1)
+        return fail(LP_E_SIZE, "padding %lld x %lld smaller than n + k - 1 = %lld x %lld",
+                    (long long)py, (long long)px, (long long)(p->ny + p->ky - 1),
+                    (long long)(p->nx + p->kx - 1));
+    if (!is_5smooth(py) || !is_5smooth(px))
+        return fail(LP_E_SIZE, "padding %lld x %lld is not of the form 2^a 3^b 5^c",
+                    (long long)py, (long long)px);
+    if (px % 2 != 0) return fail(LP_E_SIZE, "padded row length %lld must be even", (long long)px);
+    if (py > LP_MAX_PY || px > LP_MAX_PX)
+        return fail(LP_E_SIZE, "padding %lld x %lld beyond the maximum %d x %d", (long long)py,
+                    (long long)px, LP_MAX_PY, LP_MAX_PX);
+    p->py = py;
+    p->px = px;
+    p->m = px / 2;
+    p->h = p->m + 1;
+    make_fft(p->m, &p->fx, &p->twx);
+    make_fft(p->py, &p->fy, &p->twy);
+    p->rtw.assign(2 * (p->m + 1), 0.f);
+    for (int64_t k = 0; k <= p->m; ++k) {
+        double c, s;
+        exp_frac(k, p->px, &c, &s);
+        p->rtw[2 * k] = static_cast<float>(c);
+        p->rtw[2 * k + 1] = static_cast<float>(-s);
+    }
+    choose_shape(p);
+    layout(p);
+    return LP_OK;
+}
+
+lp::RowArgs row_args(const lp_plan *p)
+{
+    lp::RowArgs a{};
+    a.ny = static_cast<int32_t>(p->ny);
+    a.nx = static_cast<int32_t>(p->nx);
+    a.m = static_cast<int32_t>(p->m);
+    a.h = static_cast<int32_t>(p->h);
+    a.logc = p->logc;
+    a.logb = p->logb;
+    a.nblk = static_cast<int32_t>(p->nblk);
+    a.fx = p->fx;
+    a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twx);
+    a.rtw = reinterpret_cast<const float2 *>(p->ws + p->off_rtw);
+    return a;
+}
+
+lp::ColArgs col_args(const lp_plan *p)
+{
+    lp::ColArgs a{};
+    a.ny = static_cast<int32_t>(p->ny);
+    a.py = static_cast<int32_t>(p->py);
+    a.logc = p->logc;
+    a.nblk = static_cast<int32_t>(p->nblk);
+    a.ku = static_cast<int32_t>(p->form == LP_FORM_REAL_QUADRANT ? p->py / 2 + 1 : p->py);
+    a.fy = p->fy;
+    a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twy);
+    a.kh = p->ws + p->off_kh;
+    return a;
+}
+
+bool attributes_set = false;
+
+int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *who)
+{
+    if (!p) return fail(LP_E_INVALID, "%s: null plan", who);
+    if (!in || !out) return fail(LP_E_INVALID, "%s: null data pointer", who);
+    if (!p->bound) return fail(LP_E_NOMEM, "%s: no workspace bound", who);
+    if (p->form == LP_FORM_NONE) return fail(LP_E_STATE, "%s: kernel spectrum not computed", who);
+    hipError_t e;
+    const bool rec = p->timing && p->ev_calls < kMaxTimedCalls;
+    hipEvent_t *ev = rec ? &p->ev[4 * p->ev_calls] : nullptr;
+    if (rec && (e = hipEventRecord(ev[0], p->stream)) != hipSuccess) return fail_hip(e, who);
+    float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
+    const lp::RowArgs ra = row_args(p);
+    const lp::ColArgs ca = col_args(p);
+    if ((e = lp::launch_rows_r2c(in, W, ra, p->t_rows, p->stream)) != hipSuccess)
+        return fail_hip(e, "rows forward launch");
+    if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
+    if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream)) != hipSuccess)
+        return fail_hip(e, "column stage launch");
+    if (rec && (e = hipEventRecord(ev[2], p->stream)) != hipSuccess) return fail_hip(e, who);
+    if ((e = lp::launch_rows_c2r(W, out, ra, p->t_rows, p->stream)) != hipSuccess)
+        return fail_hip(e, "rows inverse launch");
+    if (rec) {
+        if ((e = hipEventRecord(ev[3], p->stream)) != hipSuccess) return fail_hip(e, who);
+        ++p->ev_calls;
+    }
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lp_last_error(void) { return g_err.c_str(); }
+
+int lp_last_status(void) { return g_status; }
+
+const char *lp_version(void) { return "lp 0.1 (gfx950, LDS Stockham 2/3/4/5/8)"; }
+
+lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double pitch_km)
+{
+    clear_error();
+    if (ny <= 0 || nx <= 0 || ky <= 0 || kx <= 0) {
+        fail(LP_E_INVALID, "sizes must be positive (ny=%lld nx=%lld ky=%lld kx=%lld)",
+             (long long)ny, (long long)nx, (long long)ky, (long long)kx);
+        return nullptr;
+    }
+    if (!(pitch_km > 0.0) || !std::isfinite(pitch_km)) {
+        fail(LP_E_INVALID, "pitch must be positive and finite");
+        return nullptr;
+    }
+    if (ny + ky - 1 > LP_MAX_PY || nx + kx - 1 > LP_MAX_PX) {
+        fail(LP_E_SIZE, "n + k - 1 = %lld x %lld beyond the maximum %d x %d",
+             (long long)(ny + ky - 1), (long long)(nx + kx - 1), LP_MAX_PY, LP_MAX_PX);
+        return nullptr;
+    }
+    lp_plan *p = new (std::nothrow) lp_plan();
+    if (!p) {
+        fail(LP_E_NOMEM, "out of host memory");
+        return nullptr;
+    }
+    p->ny = ny; p->nx = nx; p->ky = ky; p->kx = kx; p->pitch = pitch_km;
+    const int64_t py = next_5smooth(ny + ky - 1, false);
+    const int64_t px = next_5smooth(nx + kx - 1, true);
+    if (set_padding(p, py, px) != LP_OK) {
+        delete p;
+        return nullptr;
+    }
+    return p;
+}
+
+void lp_plan_destroy(lp_plan *p)
+{
+    if (!p) return;
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    delete p;
+}
+
+int lp_plan_set_padding(lp_plan *p, int64_t py, int64_t px)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (p->bound) return fail(LP_E_STATE, "padding must be set before lp_plan_bind");
+    return set_padding(p, py, px);
+}
+
+int lp_plan_get_padding(const lp_plan *p, int64_t *py, int64_t *px)
+{
+    clear_error();
+    if (!p || !py || !px) return fail(LP_E_INVALID, "null argument");
+    *py = p->py;
+    *px = p->px;
+    return LP_OK;
+}
+
+size_t lp_plan_workspace_bytes(const lp_plan *p) { return p ? p->bytes : 0; }
+
+int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (cols_per_group) *cols_per_group = 1 << p->logc;
+    if (rows_per_group) *rows_per_group = 1 << p->logb;
+    return LP_OK;
+}
+
+int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (!ws) return fail(LP_E_INVALID, "null workspace");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LP_E_INVALID, "workspace not 256-byte aligned");
+    if (bytes < p->bytes)
+        return fail(LP_E_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, p->bytes);
+    hipError_t e;
+    if (!attributes_set) {
+        if ((e = lp::set_kernel_attributes()) != hipSuccess) return fail_hip(e, "kernel attributes");
+        attributes_set = true;
+    }
+    p->ws = static_cast<char *>(ws);
+    p->ws_bytes = bytes;
+    p->stream = static_cast<hipStream_t>(stream);
+    p->bound = false;
+    p->form = LP_FORM_NONE;
+    struct { size_t off; const std::vector<float> *v; } up[] = {
+        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}};
+    for (auto &u : up)
+        if ((e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
+                                p->stream)) != hipSuccess)
+            return fail_hip(e, "twiddle upload");
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "twiddle upload");
+    p->bound = true;
+    return LP_OK;
+}
+
+int lp_kernel_spectrum(lp_plan *p, const double *psf)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (!psf) return fail(LP_E_INVALID, "null kernel");
+    const int64_t ky = p->ky, kx = p->kx;
+    for (int64_t i = 0; i < ky * kx; ++i)
+        if (!std::isfinite(psf[i])) return fail(LP_E_INVALID, "kernel entry %lld is not finite", (long long)i);
+    if (!p->bound) return fail(LP_E_STATE, "lp_kernel_spectrum before lp_plan_bind");
+    // Exact mirror symmetry on both axes (odd sizes) => real, even spectrum.
+    bool sym = (ky % 2 == 1) && (kx % 2 == 1);
+    for (int64_t a = 0; sym && a < ky; ++a)
+        for (int64_t b = 0; b < kx; ++b) {
+            const double v = psf[a * kx + b];
+            if (v != psf[(ky - 1 - a) * kx + b] || v != psf[a * kx + (kx - 1 - b)]) { sym = false; break; }
+        }
+    const int form = sym ? LP_FORM_REAL_QUADRANT : LP_FORM_COMPLEX;
+    // FP64 twiddle tables exp(-2 pi i m / N)
+    std::vector<double> tabx(2 * p->px), taby(2 * p->py);
+    for (int64_t m = 0; m < p->px; ++m) {
+        double c, s;
+        exp_frac(m, p->px, &c, &s);
+        tabx[2 * m] = c;
+        tabx[2 * m + 1] = -s;
+    }
+    for (int64_t m = 0; m < p->py; ++m) {
+        double c, s;
+        exp_frac(m, p->py, &c, &s);
+        taby[2 * m] = c;
+        taby[2 * m + 1] = -s;
+    }
+    // scratch (overlaps the intermediate, unused until lp_convolve)
+    char *sc = p->ws + p->off_w;
+    double *dK = reinterpret_cast<double *>(sc);
+    double2 *dT1 = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8));
+    double2 *dTabx = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8) + align256(ky * p->h * 16));
+    double2 *dTaby = reinterpret_cast<double2 *>(reinterpret_cast<char *>(dTabx) + align256(p->px * 16));
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dK, psf, ky * kx * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(dTabx, tabx.data(), tabx.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(dTaby, taby.data(), taby.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+        return fail_hip(e, "kernel upload");
+    const int cy = static_cast<int>((ky - 1) / 2), cx = static_cast<int>((kx - 1) / 2);
+    if ((e = lp::launch_spec_rows(dK, static_cast<int>(ky), static_cast<int>(kx), cx,
+                                  static_cast<int>(p->px), static_cast<int>(p->h), dTabx, dT1,
+                                  p->stream)) != hipSuccess)
+        return fail_hip(e, "spectrum rows launch");
+    const int ku = static_cast<int>(sym ? p->py / 2 + 1 : p->py);
+    const double scale = 1.0 / (static_cast<double>(p->py) * static_cast<double>(p->px));
+    if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), cy, static_cast<int>(p->py), ku,
+                                  static_cast<int>(p->h), p->logc, static_cast<int>(p->nblk), dTaby,
+                                  scale, form, p->ws + p->off_kh, p->stream)) != hipSuccess)
+        return fail_hip(e, "spectrum columns launch");
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "kernel spectrum");
+    p->form = form;
+    return LP_OK;
+}
+
+int lp_plan_spectrum_form(const lp_plan *p) { return p ? p->form : LP_FORM_NONE; }
+
+int lp_plan_read_spectrum(lp_plan *p, float *out)
+{
+    clear_error();
+    if (!p || !out) return fail(LP_E_INVALID, "null argument");
+    if (p->form == LP_FORM_NONE) return fail(LP_E_STATE, "kernel spectrum not computed");
+    const int64_t C = int64_t{1} << p->logc;
+    const bool q = p->form == LP_FORM_REAL_QUADRANT;
+    const int64_t ku = q ? p->py / 2 + 1 : p->py;
+    const size_t elt = q ? 4 : 8;
+    std::vector<float> blk(static_cast<size_t>(p->nblk) * ku * C * elt / 4);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(blk.data(), p->ws + p->off_kh, blk.size() * 4, hipMemcpyDeviceToHost,
+                            p->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(p->stream)) != hipSuccess)
+        return fail_hip(e, "spectrum read");
+    for (int64_t u = 0; u < p->py; ++u)
+        for (int64_t v = 0; v < p->h; ++v) {
+            const int64_t vb = v / C, c = v % C;
+            float re, im;
+            if (q) {
+                const int64_t uq = (2 * u <= p->py) ? u : p->py - u;
+                re = blk[(vb * ku + uq) * C + c];
+                im = 0.f;
+            } else {
+                const int64_t i = ((vb * ku + u) * C + c) * 2;
+                re = blk[i];
+                im = blk[i + 1];
+            }
+            out[(u * p->h + v) * 2] = re;
+            out[(u * p->h + v) * 2 + 1] = im;
+        }
+    return LP_OK;
+}
+
+int lp_convolve(lp_plan *p, const float *radiance, float *out)
+{
+    clear_error();
+    return run_path(p, radiance, out, false, "lp_convolve");
+}
+
+int lp_adjoint(lp_plan *p, const float *grad_out, float *grad_in)
+{
+    clear_error();
+    return run_path(p, grad_out, grad_in, true, "lp_adjoint");
+}
+
+int lp_plan_timing(lp_plan *p, int enable)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (enable && p->ev.empty()) {
+        p->ev.resize(4 * kMaxTimedCalls);
+        for (auto &e : p->ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) {
+                p->ev.clear();
+                return fail_hip(r, "event create");
+            }
+        }
+    }
+    p->timing = enable != 0;
+    p->ev_calls = 0;
+    return LP_OK;
+}
+
+int lp_plan_stage_ms(lp_plan *p, double *ms, int n, int *calls)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    double acc[3] = {0, 0, 0};
+    if (p->ev_calls > 0) {
+        hipError_t e = hipEventSynchronize(p->ev[4 * p->ev_calls - 1]);
+        if (e != hipSuccess) return fail_hip(e, "event sync");
+        for (int c = 0; c < p->ev_calls; ++c)
+            for (int s = 0; s < 3; ++s) {
+                float t = 0.f;
+                e = hipEventElapsedTime(&t, p->ev[4 * c + s], p->ev[4 * c + s + 1]);
+                if (e != hipSuccess) return fail_hip(e, "event elapsed");
+                acc[s] += t;
+            }
+    }
+    for (int s = 0; s < n && s < 3; ++s)
+        if (ms) ms[s] = acc[s];
+    if (calls) *calls = p->ev_calls;
+    p->ev_calls = 0;
+    return LP_OK;
+}
+
+}  // extern "C"

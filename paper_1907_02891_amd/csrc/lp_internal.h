@@ -1,0 +1,75 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+// Not part of the public ABI (include/lp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lp {
+
+// Largest LDS allocation one workgroup may take on gfx950 (160 KiB per CU).
+constexpr int kLdsBytes = 163840;
+// Largest number of complex values one thread holds during a pass.
+constexpr int kEltsPerThread = 20;
+constexpr int kMaxPasses = 16;
+
+// One radix pass of a Stockham autosort transform of length n = product of
+// radices.  `p` is the product of the radices of the earlier passes (the
+// length of the sub-transforms already formed), `nb` = n / radix the number
+// of butterflies, `tw` the offset of this pass's twiddles in the table:
+// tw[tw + k*(radix-1) + (j-1)] = exp(-2 pi i j k / (p * radix)), 0<=k<p.
+struct FftPass {
+    int32_t radix;
+    int32_t p;
+    int32_t nb;
+    int32_t tw;
+    float inv_p;  // 1.0f / p, for the exact quotient of indices < 2^15
+};
+
+struct FftDesc {
+    int32_t n;
+    int32_t npass;
+    FftPass pass[kMaxPasses];
+};
+
+// Row stage arguments (forward real-to-complex with implicit zero padding,
+// or inverse complex-to-real with the crop).
+struct RowArgs {
+    int32_t ny, nx;     // map
+    int32_t m;          // half padded row length Px/2 (the complex length)
+    int32_t h;          // Px/2 + 1 stored columns
+    int32_t logc;       // log2 columns per block of the blocked layout
+    int32_t logb;       // log2 rows per workgroup
+    int32_t nblk;       // column blocks = ceil(h / 2^logc)
+    FftDesc fx;         // complex transform of length m
+    const float2 *tw;   // its twiddles
+    const float2 *rtw;  // exp(-2 pi i k / Px), 0 <= k <= m
+};
+
+// Column stage arguments (forward transform, spectrum multiply, inverse).
+struct ColArgs {
+    int32_t ny;         // stored rows of the intermediate
+    int32_t py;         // padded column length
+    int32_t logc;       // log2 columns per workgroup (= per block)
+    int32_t nblk;
+    int32_t ku;         // stored spectrum rows per block (py or py/2+1)
+    FftDesc fy;
+    const float2 *tw;
+    const void *kh;     // blocked spectrum (float2 complex or float real)
+};
+
+// Launchers (lp_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_rows_r2c(const float *R, float2 *W, const RowArgs &a, int threads,
+                           hipStream_t s);
+hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, int threads,
+                            hipStream_t s);
+hipError_t launch_rows_c2r(const float2 *W, float *S, const RowArgs &a, int threads,
+                           hipStream_t s);
+hipError_t launch_spec_rows(const double *K, int ky, int kx, int cx, int px, int h,
+                            const double2 *tabx, double2 *t1, hipStream_t s);
+hipError_t launch_spec_cols(const double2 *t1, int ky, int cy, int py, int ku, int h,
+                            int logc, int nblk, const double2 *taby, double scale,
+                            int form, void *kh, hipStream_t s);
+hipError_t set_kernel_attributes();
+
+}  // namespace lp

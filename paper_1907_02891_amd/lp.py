@@ -1,0 +1,243 @@
+"""Python binding of the C ABI in include/lp.h (argument marshalling only).
+
+Every step of the computation runs in the HIP library liblp.so; this module
+loads it with ctypes, hands it torch device pointers and the current HIP
+stream, and turns error codes into exceptions.  If the library is missing the
+import fails: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+# torch first: its bundled HIP runtime (soname libamdhip64.so.7) must be the
+# one liblp.so binds to, so that both share one runtime and one device context.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1907_02891_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+LP_OK, LP_E_INVALID, LP_E_SIZE, LP_E_STATE, LP_E_NOMEM, LP_E_DEVICE = 0, -1, -2, -3, -4, -5
+FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
+MAX_PY, MAX_PX = 20480, 40958
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_ip = ctypes.POINTER(ctypes.c_int)
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+
+_SIGS = {
+    "lp_last_error": ([], ctypes.c_char_p),
+    "lp_version": ([], ctypes.c_char_p),
+    "lp_last_status": ([], ctypes.c_int),
+    "lp_plan_create": ([_i64, _i64, _i64, _i64, ctypes.c_double], _vp),
+    "lp_plan_destroy": ([_vp], None),
+    "lp_plan_set_padding": ([_vp, _i64, _i64], ctypes.c_int),
+    "lp_plan_get_padding": ([_vp, _i64p, _i64p], ctypes.c_int),
+    "lp_plan_workspace_bytes": ([_vp], ctypes.c_size_t),
+    "lp_plan_bind": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "lp_kernel_spectrum": ([_vp, _dp], ctypes.c_int),
+    "lp_plan_spectrum_form": ([_vp], ctypes.c_int),
+    "lp_plan_read_spectrum": ([_vp, _fp], ctypes.c_int),
+    "lp_convolve": ([_vp, _vp, _vp], ctypes.c_int),
+    "lp_adjoint": ([_vp, _vp, _vp], ctypes.c_int),
+    "lp_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_stage_ms": ([_vp, _dp, ctypes.c_int, _ip], ctypes.c_int),
+    "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class LPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def last_error() -> str:
+    return _lib.lp_last_error().decode()
+
+
+def version() -> str:
+    return _lib.lp_version().decode()
+
+
+def _check(rc):
+    if rc != LP_OK:
+        raise LPError(rc, last_error())
+    return rc
+
+
+def raw():
+    """The ctypes library handle (for tests of the C ABI itself)."""
+    return _lib
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """One map shape and one kernel (lp_plan_*).  Host-only until bind()."""
+
+    def __init__(self, ny, nx, ky, kx, pitch_km=0.5, padding=None):
+        self._p = _lib.lp_plan_create(int(ny), int(nx), int(ky), int(kx), float(pitch_km))
+        if not self._p:
+            raise LPError(_lib.lp_last_status(), last_error())
+        self.ny, self.nx, self.ky, self.kx = int(ny), int(nx), int(ky), int(kx)
+        self.workspace = None
+        self.stream = None
+        if padding is not None:
+            self.set_padding(*padding)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.lp_plan_destroy(self._p)
+            self._p = None
+
+    __del__ = close
+
+    @property
+    def handle(self):
+        return self._p
+
+    def set_padding(self, py, px):
+        _check(_lib.lp_plan_set_padding(self._p, int(py), int(px)))
+
+    @property
+    def padding(self):
+        py, px = _i64(), _i64()
+        _check(_lib.lp_plan_get_padding(self._p, ctypes.byref(py), ctypes.byref(px)))
+        return py.value, px.value
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.lp_plan_workspace_bytes(self._p))
+
+    @property
+    def shape(self):
+        c, b = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.lp_plan_shape(self._p, ctypes.byref(c), ctypes.byref(b)))
+        return c.value, b.value
+
+    def bind(self, device=None, stream=None, workspace=None):
+        """Allocate (or take) a torch uint8 device workspace and bind it with
+        `stream` (default: torch's current stream)."""
+        import torch
+        if workspace is None:
+            dev = torch.device("cuda") if device is None else torch.device(device)
+            workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        ptr = workspace.data_ptr()
+        off = (-ptr) % 256
+        self.workspace = workspace
+        self.stream = torch.cuda.current_stream(workspace.device) if stream is None else stream
+        _check(_lib.lp_plan_bind(self._p, ctypes.c_void_p(ptr + off),
+                                 workspace.numel() - off, _stream_ptr(self.stream)))
+        return self
+
+    def set_kernel(self, psf):
+        psf = np.ascontiguousarray(psf, dtype=np.float64)
+        if psf.shape != (self.ky, self.kx):
+            raise ValueError(f"kernel shape {psf.shape} != ({self.ky}, {self.kx})")
+        _check(_lib.lp_kernel_spectrum(self._p, psf.ctypes.data_as(_dp)))
+        return self
+
+    @property
+    def form(self):
+        return int(_lib.lp_plan_spectrum_form(self._p))
+
+    def read_spectrum(self):
+        """Stored spectrum (scaled by 1/(Py Px)) as complex64 Py x (Px/2+1)."""
+        py, px = self.padding
+        out = np.empty((py, px // 2 + 1, 2), np.float32)
+        _check(_lib.lp_plan_read_spectrum(self._p, out.ctypes.data_as(_fp)))
+        return out[..., 0] + 1j * out[..., 1]
+
+    def _io(self, x, out):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                and x.is_contiguous() and tuple(x.shape) == (self.ny, self.nx)):
+            raise ValueError(f"expected a contiguous float32 CUDA tensor of shape ({self.ny}, {self.nx})")
+        if out is None:
+            out = torch.empty_like(x)
+        elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+                  and tuple(out.shape) == (self.ny, self.nx)):
+            raise ValueError("bad output tensor")
+        return out
+
+    def convolve(self, radiance, out=None):
+        """S = K (*) R, "same" size, on the bound stream (lp_convolve)."""
+        out = self._io(radiance, out)
+        _check(_lib.lp_convolve(self._p, ctypes.c_void_p(radiance.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def adjoint(self, grad_out, out=None):
+        """Transposed operator (lp_adjoint)."""
+        out = self._io(grad_out, out)
+        _check(_lib.lp_adjoint(self._p, ctypes.c_void_p(grad_out.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def timing(self, enable=True):
+        _check(_lib.lp_plan_timing(self._p, int(bool(enable))))
+
+    def stage_ms(self):
+        """(per-stage summed ms [rows fwd, columns, rows inv], calls)."""
+        ms = (ctypes.c_double * 3)()
+        calls = ctypes.c_int()
+        _check(_lib.lp_plan_stage_ms(self._p, ms, 3, ctypes.byref(calls)))
+        return list(ms), calls.value
+
+
+def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None):
+    """Plan + workspace + kernel spectrum in one call."""
+    psf = np.asarray(psf)
+    p = Plan(ny, nx, psf.shape[0], psf.shape[1], pitch_km, padding)
+    p.bind(device=device)
+    p.set_kernel(psf)
+    return p
+
+
+def _autograd():
+    import torch
+
+    class LPConvolve(torch.autograd.Function):
+        """S = conv(R) with gradient grad_R = conv^T(grad_S) (lp_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, radiance, plan):
+            ctx.plan = plan
+            return plan.convolve(radiance.contiguous())
+
+        @staticmethod
+        def backward(ctx, grad_s):
+            return ctx.plan.adjoint(grad_s.contiguous()), None
+
+    return LPConvolve
+
+
+_LPConvolve = None
+
+
+def convolve(radiance, plan):
+    """Differentiable "same" convolution through the plan."""
+    global _LPConvolve
+    if _LPConvolve is None:
+        _LPConvolve = _autograd()
+    return _LPConvolve.apply(radiance, plan)

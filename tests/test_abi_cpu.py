@@ -1,0 +1,141 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function include/lp.h declares, and rejects bad arguments and out-of-order
+calls before touching the HIP runtime."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1907_02891_amd import lp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "lp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert "lp_convolve" in names and "lp_kernel_spectrum" in names
+    lib = lp.raw()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(lp.EXPORTED) | set(names)
+
+
+def test_version():
+    assert "gfx950" in lp.version()
+
+
+@pytest.mark.parametrize("args", [(0, 4, 3, 3, 0.5), (4, -1, 3, 3, 0.5), (4, 4, 0, 3, 0.5),
+                                  (4, 4, 3, 3, 0.0), (4, 4, 3, 3, float("nan")),
+                                  (4, 4, 3, 3, float("inf")), (4, 4, 3, 3, -1.0)])
+def test_create_rejects_bad_arguments(args):
+    assert not lp.raw().lp_plan_create(*args)
+    assert lp.last_error()
+    with pytest.raises(lp.LPError) as ei:
+        lp.Plan(*args[:4], pitch_km=args[4])
+    assert ei.value.code == lp.LP_E_INVALID
+
+
+def test_create_rejects_oversize():
+    with pytest.raises(lp.LPError) as ei:
+        lp.Plan(20000, 100, 2001, 3)
+    assert ei.value.code == lp.LP_E_SIZE
+
+
+@pytest.mark.parametrize("shape,pad", [((256, 256, 101, 101), (360, 360)),
+                                       ((4096, 4096, 1201, 1201), (5400, 5400)),
+                                       ((16384, 16384, 2001, 2001), (18432, 18432)),
+                                       ((2048, 2048, 801, 801), (2880, 2880)),
+                                       ((10, 7, 3, 3), (12, 10)),
+                                       ((1, 1, 1, 1), (1, 2))])
+def test_default_padding_is_smallest_5smooth(shape, pad):
+    p = lp.Plan(*shape)
+    assert p.padding == pad
+
+
+def is_5smooth(n):
+    for f in (2, 3, 5):
+        while n % f == 0:
+            n //= f
+    return n == 1
+
+
+@pytest.mark.parametrize("n", [7, 31, 100, 1711, 4321])
+def test_default_padding_property(n):
+    p = lp.Plan(n, n + 3, 5, 8)
+    py, px = p.padding
+    assert py >= n + 4 and px >= n + 10 and px % 2 == 0
+    assert is_5smooth(py) and is_5smooth(px)
+    assert not any(is_5smooth(m) for m in range(n + 4, py))
+    assert not any(is_5smooth(m) and m % 2 == 0 for m in range(n + 10, px))
+
+
+@pytest.mark.parametrize("pad,code", [((355, 360), lp.LP_E_SIZE), ((360, 355), lp.LP_E_SIZE),
+                                      ((364, 360), lp.LP_E_SIZE), ((360, 375), lp.LP_E_SIZE),
+                                      ((21870, 512), lp.LP_E_SIZE), ((375, 512), None),
+                                      ((512, 512), None)])
+def test_set_padding_validation(pad, code):
+    p = lp.Plan(256, 256, 101, 101)
+    if code is None:
+        p.set_padding(*pad)
+        assert p.padding == pad
+    else:
+        with pytest.raises(lp.LPError) as ei:
+            p.set_padding(*pad)
+        assert ei.value.code == code
+        assert p.padding == (360, 360)
+
+
+def test_workspace_grows_with_padding():
+    p = lp.Plan(256, 256, 101, 101)
+    a = p.workspace_bytes
+    p.set_padding(512, 512)
+    assert p.workspace_bytes > a > 0
+    assert lp.raw().lp_plan_workspace_bytes(None) == 0
+
+
+def test_state_errors_before_any_device_call():
+    lib = lp.raw()
+    p = lp.Plan(64, 48, 5, 5)
+    fake = ctypes.c_void_p(256)
+    # convolve with no workspace bound
+    assert lib.lp_convolve(p.handle, fake, fake) == lp.LP_E_NOMEM
+    assert lib.lp_adjoint(p.handle, fake, fake) == lp.LP_E_NOMEM
+    # null data pointers
+    assert lib.lp_convolve(p.handle, None, fake) == lp.LP_E_INVALID
+    assert lib.lp_convolve(None, fake, fake) == lp.LP_E_INVALID
+    # spectrum before bind
+    K = np.ones((5, 5))
+    assert lib.lp_kernel_spectrum(p.handle, K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lp.LP_E_STATE
+    # non-finite kernel rejected first
+    K[2, 3] = np.nan
+    assert lib.lp_kernel_spectrum(p.handle, K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lp.LP_E_INVALID
+    assert "not finite" in lp.last_error()
+    K[2, 3] = np.inf
+    assert lib.lp_kernel_spectrum(p.handle, K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lp.LP_E_INVALID
+    # bind: null, misaligned, too small
+    assert lib.lp_plan_bind(p.handle, None, 1 << 30, None) == lp.LP_E_INVALID
+    assert lib.lp_plan_bind(p.handle, ctypes.c_void_p(4096 + 8), 1 << 30, None) == lp.LP_E_INVALID
+    assert lib.lp_plan_bind(p.handle, ctypes.c_void_p(4096), 16, None) == lp.LP_E_NOMEM
+    # spectrum readback before spectrum
+    out = np.empty(10, np.float32)
+    assert lib.lp_plan_read_spectrum(p.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))) == lp.LP_E_STATE
+    assert lib.lp_plan_spectrum_form(p.handle) == lp.FORM_NONE
+
+
+def test_shape_choice_fits_lds():
+    for shape in [(256, 256, 101, 101), (4096, 4096, 1201, 1201), (16384, 16384, 2001, 2001),
+                  (2048, 2048, 801, 801), (3, 5, 2, 2)]:
+        p = lp.Plan(*shape)
+        py, px = p.padding
+        c, b = p.shape
+        assert c >= 1 and b >= 1 and (c & (c - 1)) == 0 and (b & (b - 1)) == 0
+        assert py * c * 8 <= 163840
+        assert (px // 2 + 1) * b * 8 <= 163840

@@ -1,0 +1,198 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerance (from the target statement of the method): relative L2 error
+<= 1e-5 and max |error| <= 1e-5 * max |S|, element by element on the same
+seeded inputs.  Full fields at sizes the oracle finishes in seconds (spanning
+several workgroup tiles and a ragged tail); sampled pixels at full workload
+sizes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import spectrum
+from paper_1907_02891_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU test without a GPU"
+    return t
+
+
+@pytest.fixture(scope="module")
+def lp(torch):
+    from paper_1907_02891_amd import lp as _lp
+    return _lp
+
+
+def gpu_run(lp, torch, R, K, padding=None, adjoint=False):
+    plan = lp.make_plan(K, *R.shape, padding=padding)
+    x = torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda()
+    y = plan.adjoint(x) if adjoint else plan.convolve(x)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), plan
+
+
+def assert_parity(S, ref, tol=TOL, label=""):
+    e2, em = oracle.rel_l2(S, ref), oracle.max_err_frac(S, ref)
+    print(f"{label} rel-L2 {e2:.3e} max-err/max|S| {em:.3e}", flush=True)
+    assert e2 <= tol and em <= tol, (label, e2, em)
+    return e2, em
+
+
+def sym_kernel(rng, ky, kx):
+    """Kernel with K(cy+d, cx+e) = Q(|d|, |e|): bitwise mirror-symmetric on
+    both axes when ky and kx are odd."""
+    cy, cx = ky // 2, kx // 2
+    Q = rng.random((cy + 1, cx + 1))
+    return Q[np.abs(np.arange(ky) - cy)][:, np.abs(np.arange(kx) - cx)]
+
+
+# ------------------------------------------------------------- small config --
+
+def test_small_workload_full_field(lp, torch):
+    R, K = synth.small_inputs()
+    S, plan = gpu_run(lp, torch, R, K, padding=(512, 512))
+    assert plan.form == lp.FORM_REAL_QUADRANT
+    assert_parity(S, oracle.conv_same(R, K), label="small 256^2 P=512")
+
+
+def test_padding_independence(lp, torch):
+    R, K = synth.small_inputs()
+    S512, _ = gpu_run(lp, torch, R, K, padding=(512, 512))
+    S360, p = gpu_run(lp, torch, R, K)
+    assert p.padding == (360, 360)
+    ref = oracle.conv_same(R, K)
+    assert_parity(S360, ref, label="small 256^2 P=360")
+    assert oracle.rel_l2(S360, S512) <= 2 * TOL
+
+
+SHAPES = [  # ny, nx, ky, kx, symmetric kernel
+    (37, 53, 9, 7, False), (64, 64, 5, 5, True), (100, 37, 31, 17, False),
+    (5, 300, 3, 41, True), (300, 5, 41, 3, False), (17, 13, 25, 31, False),
+    (1, 1, 1, 1, True), (2, 3, 2, 2, False), (129, 257, 64, 64, False),
+    (250, 250, 101, 101, True), (333, 71, 1, 1, True), (96, 200, 11, 1, False),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=[f"{s[0]}x{s[1]}k{s[2]}x{s[3]}{'s' if s[4] else 'g'}" for s in SHAPES])
+def test_ragged_shapes_full_field(lp, torch, shape):
+    ny, nx, ky, kx, sym = shape
+    rng = np.random.default_rng(100 + ny + 7 * nx + 3 * ky)
+    R = synth.radiance_map(ny, nx, 3, 0.05, (1.0, 4.0), rng) + rng.random((ny, nx)).astype(np.float32)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    S, plan = gpu_run(lp, torch, R, K)
+    assert plan.form == (lp.FORM_REAL_QUADRANT if sym and ky % 2 and kx % 2 else lp.FORM_COMPLEX)
+    assert_parity(S, oracle.conv_same(R, K), label=str(shape))
+
+
+PADS = [(27, 54), (25, 50), (32, 64), (30, 60), (48, 96), (75, 150), (64, 128), (81, 162),
+        (125, 250), (40, 160), (45, 90), (128, 256), (243, 486), (375, 1000), (512, 2)]
+
+
+@pytest.mark.parametrize("pad", PADS, ids=[f"{a}x{b}" for a, b in PADS])
+def test_every_radix_mix(lp, torch, pad):
+    """Padded sizes whose factorisations use radix 2, 3, 4, 5 and 8 passes."""
+    py, px = pad
+    rng = np.random.default_rng(py * 1000 + px)
+    ny, nx = max(1, py - 6), max(1, px - 4)
+    ky, kx = min(7, py - ny + 1), min(5, px - nx + 1)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = rng.random((ky, kx))
+    S, plan = gpu_run(lp, torch, R, K, padding=pad)
+    assert plan.padding == pad
+    assert_parity(S, oracle.conv_same(R, K), label=f"pad {pad}")
+
+
+# ---------------------------------------------------------------- spectrum --
+
+@pytest.mark.parametrize("case", [(9, 7, 24, 20, False), (11, 11, 30, 40, True),
+                                  (6, 5, 27, 50, False), (101, 101, 360, 360, True)])
+def test_spectrum_matches_oracle_dft(lp, torch, case):
+    ky, kx, py, px, sym = case
+    rng = np.random.default_rng(ky * kx + py)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx)) - 0.3
+    plan = lp.Plan(py - ky + 1, px - kx + 1, ky, kx, padding=(py, px))
+    plan.bind()
+    plan.set_kernel(K)
+    got = plan.read_spectrum()
+    ref = spectrum.kernel_spectrum(K, py, px)[:, : px // 2 + 1] / (py * px)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"spectrum {case}: max err / max {err:.2e}")
+    assert err <= 2e-7
+    assert plan.form == (lp.FORM_REAL_QUADRANT if sym else lp.FORM_COMPLEX)
+
+
+# ------------------------------------------------------------------ adjoint --
+
+@pytest.mark.parametrize("shape", [(40, 52, 9, 6, False), (64, 64, 7, 7, True), (33, 90, 12, 21, False)])
+def test_adjoint_full_field(lp, torch, shape):
+    ny, nx, ky, kx, sym = shape
+    rng = np.random.default_rng(ny + nx)
+    G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    A, _ = gpu_run(lp, torch, G, K, adjoint=True)
+    assert_parity(A, oracle.adjoint_same(G, K), label=f"adjoint {shape}")
+
+
+def test_adjoint_dot_product(lp, torch):
+    rng = np.random.default_rng(5)
+    ny, nx, ky, kx = 70, 45, 13, 8
+    K = rng.random((ky, kx))
+    R = rng.random((ny, nx)).astype(np.float32)
+    G = rng.random((ny, nx)).astype(np.float32)
+    plan = lp.make_plan(K, ny, nx)
+    CR = plan.convolve(torch.from_numpy(R).cuda()).cpu().numpy().astype(np.float64)
+    CtG = plan.adjoint(torch.from_numpy(G).cuda()).cpu().numpy().astype(np.float64)
+    lhs, rhs = np.vdot(CR, G), np.vdot(R, CtG)
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
+
+
+# -------------------------------------------------------------- invariants --
+
+def test_delta_source_reproduces_kernel(lp, torch):
+    rng = np.random.default_rng(6)
+    ny, nx, ky, kx = 60, 70, 15, 11
+    K = rng.random((ky, kx))
+    p, q = 20, 33
+    R = np.zeros((ny, nx), np.float32)
+    R[p, q] = 1.0
+    S, _ = gpu_run(lp, torch, R, K)
+    cy, cx = (ky - 1) // 2, (kx - 1) // 2
+    ref = np.zeros((ny, nx))
+    ref[p - cy:p - cy + ky, q - cx:q - cx + kx] = K
+    assert np.max(np.abs(S - ref)) <= 1e-6 * K.max()
+
+
+def test_deterministic_and_in_place(lp, torch):
+    R, K = synth.small_inputs()
+    plan = lp.make_plan(K, *R.shape, padding=(512, 512))
+    x = torch.from_numpy(R).cuda()
+    a = plan.convolve(x).cpu().numpy()
+    b = plan.convolve(x).cpu().numpy()
+    assert np.array_equal(a, b)
+    y = x.clone()
+    plan.convolve(y, out=y)
+    assert np.array_equal(y.cpu().numpy(), a)
+
+
+def test_linearity_and_sum(lp, torch):
+    rng = np.random.default_rng(8)
+    ny, nx, ky, kx = 90, 80, 21, 21
+    K = sym_kernel(rng, ky, kx)
+    R1 = np.zeros((ny, nx), np.float32)
+    R1[15:75, 15:65] = rng.random((60, 50))
+    R2 = np.zeros((ny, nx), np.float32)
+    R2[12:70, 20:60] = rng.random((58, 40))
+    plan = lp.make_plan(K, ny, nx)
+    f = lambda r: plan.convolve(torch.from_numpy(np.ascontiguousarray(r, np.float32)).cuda()).cpu().numpy().astype(np.float64)
+    S1, S2, S12 = f(R1), f(R2), f(2.0 * R1 + 0.5 * R2)
+    assert oracle.rel_l2(S12, 2.0 * S1 + 0.5 * S2) <= 1e-6
+    # zero margin >= (k-1)/2: the "same" window holds the whole sum
+    assert S1.sum() == pytest.approx(R1.astype(np.float64).sum() * K.sum(), rel=1e-5)

@@ -1,0 +1,222 @@
+"""Benchmark: output pixels/s of the FFT convolution hot path on one MI355X.
+
+One step = one lp_convolve of the whole map (rows forward transform, column
+transform x kernel spectrum x inverse, rows inverse transform with crop) with
+the map already resident in HBM.  Default workload: 4096x4096 FP32 city-cluster
+radiance map, 1201x1201 kernel d^-2.5 exp(-d/80 km) cut at 300 km (0.5 km
+pitch), padded to 5400x5400.
+
+Prints one JSON line with the throughput, a roofline entry for the dominant
+kernel (the column stage, timed with HIP events on the stream it runs on) and
+the FP64 CPU oracle timed on a bounded pixel sample on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_cols_conv_country4096.txt")
+KERNEL_SOURCES = ["paper_1907_02891_amd/csrc/lp_kernels.hip", "paper_1907_02891_amd/csrc/fft_lds.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workloads():
+    from paper_1907_02891_amd import synth
+    return {
+        "country": (synth.COUNTRY, synth.country_inputs),
+        "small": (synth.SMALL, synth.small_inputs),
+        "adjoint": (synth.ADJOINT, lambda: synth.adjoint_inputs()[:2]),
+        "continental": (synth.CONTINENTAL, synth.continental_inputs),
+    }
+
+
+def model_bytes(ny, nx, py, px, form):
+    """Algorithmic HBM bytes: whole path (three passes) and the column stage.
+
+    Whole path: read R, write S (4 B/px each), write+read the intermediate
+    after the row pass and after the column pass (2 x 2 x 8 B per stored
+    complex, ny x (Px/2+1)), read the stored spectrum once.
+    Column stage: read and write the intermediate, read the spectrum."""
+    h = px // 2 + 1
+    kh = 4 * (py // 2 + 1) * h if form == 1 else 8 * py * h
+    inter = 8 * ny * h
+    path = 4 * ny * nx + 4 * ny * nx + 4 * inter + kh
+    cols = 2 * inter + kh
+    return path, cols, kh
+
+
+def read_pmc(src_hash):
+    """HBM bytes per column-stage dispatch from a committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel sources."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_sha256") != src_hash:
+        return None
+    try:
+        f = float(vals["fetch_kib_per_dispatch"]) * float(vals.get("fetch_scale", 1.0))
+        w = float(vals["write_kib_per_dispatch"]) * float(vals.get("write_scale", 1.0))
+    except (KeyError, ValueError):
+        return None
+    return (f + w) * 1024.0
+
+
+def cpu_baseline(R, K, budget_s):
+    """The FP64 oracle (as it stands) on a seeded pixel sample, host cores."""
+    import oracle
+    rng = np.random.default_rng(99)
+    Rd = R.astype(np.float64)
+    n = 16
+    t0 = time.perf_counter()
+    oracle.conv_same_pixels(Rd, K, rng.choice(R.size, n, replace=False))
+    dt = time.perf_counter() - t0
+    n = int(max(16, min(R.size, n * budget_s / max(dt, 1e-6))))
+    idx = rng.choice(R.size, n, replace=False)
+    t0 = time.perf_counter()
+    oracle.conv_same_pixels(Rd, K, idx)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "output pixels/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} uniformly drawn output pixels of the same map, FP64 direct sum "
+                      f"over the {K.shape[0]}x{K.shape[1]} kernel, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="country", choices=["country", "small", "adjoint", "continental"])
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--check", type=int, default=256, help="sampled parity pixels (0: off)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for PMC byte calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1907_02891_amd import lp
+
+    wl, make_inputs = workloads()[args.workload]
+    t0 = time.perf_counter()
+    R, K = make_inputs()
+    t_gen = time.perf_counter() - t0
+    ny, nx = R.shape
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    t0 = time.perf_counter()
+    plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=(wl.py, wl.px))
+    plan.bind(device=dev, stream=stream)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan.set_kernel(K)
+    t_spec = time.perf_counter() - t0
+
+    x = torch.from_numpy(R).to(dev)
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        plan.convolve(x, out=y)
+    torch.cuda.synchronize()
+
+    plan.timing(True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.convolve(x, out=y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = ev0.elapsed_time(ev1)
+    stage_ms, calls = plan.stage_ms()
+    plan.timing(False)
+    ms_step = ms_total / args.steps
+    stage_avg = [s / max(calls, 1) for s in stage_ms]
+
+    py, px = plan.padding
+    path_b, cols_b, kh_b = model_bytes(ny, nx, py, px, plan.form)
+    src_hash = kernel_source_hash()
+    traffic = read_pmc(src_hash)
+    cols_s = stage_avg[1] * 1e-3
+    achieved = cols_b / cols_s / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_cols_conv", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}
+
+    out = {
+        "metric": "output pixels/s per MI355X (FP32 FFT convolution) at rel-L2 <= 1e-5",
+        "value": ny * nx / (ms_step * 1e-3),
+        "unit": "output pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
+                   "padding": [py, px], "pitch_km": wl.pitch_km,
+                   "spectrum_form": {1: "real-quadrant", 2: "complex"}[plan.form],
+                   "cols_per_group": plan.shape[0], "rows_per_group": plan.shape[1]},
+        "roofline": roofline,
+        "path": {"stage_ms": [round(s, 5) for s in stage_avg],
+                 "stage_names": ["k_rows_r2c", "k_cols_conv", "k_rows_c2r"],
+                 "model_bytes": path_b,
+                 "model_GBs": round(path_b / (ms_step * 1e-3) / 1e9, 1),
+                 "model_frac": round(path_b / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "wall_s": round(wall, 4)},
+        "setup_s": {"inputs": round(t_gen, 2), "plan_bind": round(t_plan, 3),
+                    "kernel_spectrum": round(t_spec, 3)},
+        "kernel_source": src_hash,
+    }
+
+    if args.check > 0:
+        import oracle
+        rng = np.random.default_rng(5)
+        from paper_1907_02891_amd import synth
+        idx = synth.sample_pixels(R, args.check, rng)
+        got = y.cpu().numpy().ravel()[idx]
+        ref = oracle.conv_same_pixels(R, K, idx)
+        out["parity_sample"] = {"pixels": int(idx.size), "rel_l2": oracle.rel_l2(got, ref),
+                                "max_err_frac": oracle.max_err_frac(got, ref)}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * a.numel() * 4
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(R, K, args.cpu_budget)
+        out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
+    out["paper_context"] = {"px_per_s": 3.28e6, "hardware": "Matlab R2011a, Intel Core i7 2.40 GHz",
+                            "workload": "11920x11804 map, ZSB kernel, incl. file output"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

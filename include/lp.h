@@ -152,6 +152,17 @@ int lp_adjoint(lp_plan *plan, const float *grad_out, float *grad_in);
 int lp_plan_timing(lp_plan *plan, int enable);
 int lp_plan_stage_ms(lp_plan *plan, double *ms, int n, int *calls);
 
+/* Kernel family of the column stage.  LP_KERNELS_AUTO (default): a
+ * register-resident kernel specialised at compile time for the padded column
+ * length when the library has one (three large-radix passes, the spectrum
+ * multiply in registers), else the generic LDS-staged kernel;
+ * LP_KERNELS_GENERIC: always the generic one.  lp_plan_kernels reports which
+ * family lp_convolve will run (LP_KERNELS_SPECIALISED or LP_KERNELS_GENERIC;
+ * -1 for a NULL plan). */
+enum { LP_KERNELS_AUTO = 0, LP_KERNELS_GENERIC = 1, LP_KERNELS_SPECIALISED = 2 };
+int lp_plan_set_kernels(lp_plan *plan, int which);
+int lp_plan_kernels(const lp_plan *plan);
+
 /* Launch shape the plan chose (host pointers, any may be NULL): columns per
  * workgroup of the column stage, rows per workgroup of the row stages. */
 int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);

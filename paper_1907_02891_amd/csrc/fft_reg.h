@@ -1,0 +1,215 @@
+// Register-resident mixed-radix transforms with compile-time sizes.
+//
+// A transform of length N = R0 * R1 * R2 is done in three Stockham passes of
+// large radix; each pass runs an R-point DFT entirely in registers, built at
+// compile time from 2/3/4/5/8-point kernels by Cooley-Tukey splitting with
+// constant internal twiddles.  Data stay in registers; LDS is only the
+// exchange buffer between passes (two exchanges per transform), padded by one
+// word in 32 against bank conflicts.  Pass twiddles come from FP32 tables
+// generated in FP64 on the host.
+#pragma once
+
+#include <utility>
+
+#include "fft_lds.h"
+
+namespace lp {
+
+// ------------------------------------------------------------------------
+// Compile-time cos/sin of 2 pi m / n: exact integer reduction to an octant,
+// then Taylor series in double for the remaining angle in [0, pi/4].
+struct CPair {
+    double c, s;
+};
+
+constexpr double kQuarterPi = 0.785398163397448309615660845819875721;
+
+constexpr double taylor_sin(double x)
+{
+    double t = x, s = x;
+    for (int n = 1; n < 24; ++n) {
+        t *= -x * x / ((2.0 * n) * (2.0 * n + 1.0));
+        s += t;
+    }
+    return s;
+}
+
+constexpr double taylor_cos(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int n = 1; n < 24; ++n) {
+        t *= -x * x / ((2.0 * n - 1.0) * (2.0 * n));
+        s += t;
+    }
+    return s;
+}
+
+constexpr CPair cexp2pi(long m, long n)
+{
+    m %= n;
+    if (m < 0) m += n;
+    const long m8 = 8 * m, o = m8 / n;
+    const double phi = (o % 2 == 0) ? kQuarterPi * double(m8 - o * n) / double(n)
+                                    : kQuarterPi * double((o + 1) * n - m8) / double(n);
+    const double cp = taylor_cos(phi), sp = taylor_sin(phi);
+    switch (o) {
+        case 0: return {cp, sp};
+        case 1: return {sp, cp};
+        case 2: return {-sp, cp};
+        case 3: return {-cp, sp};
+        case 4: return {-cp, -sp};
+        case 5: return {-sp, -cp};
+        case 6: return {sp, -cp};
+        default: return {cp, -sp};
+    }
+}
+
+// a * exp(-/+ 2 pi i M / R) with M, R compile-time; trivial angles skip the
+// multiply.
+template <int M, int R, bool INV>
+__device__ __forceinline__ float2 twc(float2 a)
+{
+    constexpr int m = ((M % R) + R) % R;
+    if constexpr (m == 0) {
+        return a;
+    } else if constexpr (2 * m == R) {
+        return make_float2(-a.x, -a.y);
+    } else if constexpr (4 * m == R) {
+        return rot<INV>(a);
+    } else if constexpr (4 * m == 3 * R) {
+        return rot<!INV>(a);
+    } else {
+        constexpr CPair e = cexp2pi(m, R);
+        constexpr float c = static_cast<float>(e.c);
+        constexpr float s = INV ? static_cast<float>(e.s) : -static_cast<float>(e.s);
+        return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+}
+
+// Compile-time loop: f(std::integral_constant<int, 0>) ... (N-1).
+template <typename F, int... I>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+constexpr int first_factor(int r)
+{
+    if (r % 4 == 0 && r != 4 && r != 8) return 4;
+    if (r % 2 == 0) return 2;
+    if (r % 3 == 0) return 3;
+    return 5;
+}
+
+constexpr bool is_base_radix(int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8; }
+
+// In-place R-point DFT of x[0..R-1] (forward sign -, inverse +, unnormalised).
+// Composite R = A * B: n = B a + b, k = k1 + A k2;
+// y[k1 + A k2] = sum_b w_B^{b k2} [ w_R^{b k1} sum_a x[B a + b] w_A^{a k1} ].
+template <int R, bool INV>
+__device__ __forceinline__ void dftc(float2 *x)
+{
+    if constexpr (R == 1) {
+    } else if constexpr (is_base_radix(R)) {
+        dft<R, INV>(x);
+    } else {
+        constexpr int A = first_factor(R), B = R / A;
+        float2 t[R];
+        sfor<B>([&](auto bi) {
+            constexpr int b = decltype(bi)::value;
+            float2 u[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) u[a] = x[B * a + b];
+            dftc<A, INV>(u);
+            sfor<A>([&](auto ki) {
+                constexpr int k1 = decltype(ki)::value;
+                t[b * A + k1] = twc<b * k1, R, INV>(u[k1]);
+            });
+        });
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+            float2 w[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) w[b] = t[b * A + k1];
+            dftc<B, INV>(w);
+#pragma unroll
+            for (int k2 = 0; k2 < B; ++k2) x[k1 + A * k2] = w[k2];
+        }
+    }
+}
+
+// LDS word index with one pad word per 32.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
+constexpr int lds_words(int n) { return n + (n >> 5) + 1; }
+
+// One pass of radix R over a length-N transform, with P = product of the
+// radices of earlier passes; G interleaved transforms per workgroup
+// (element n of transform g at LDS word lpad(n * G + g)); thread (tt, g) with
+// tt in [0, TF) takes butterflies i = tt + s * TF.
+template <int N, int R, int P, int TF, int G>
+struct RegPass {
+    static constexpr int NB = N / R;
+    static constexpr int S = (NB + TF - 1) / TF;
+
+    // inputs of butterfly i: element i + j * NB
+    __device__ __forceinline__ static void load(float2 (&v)[S][R], const float2 *lds, int tt, int g)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tt + s * TF;
+            if (NB % TF == 0 || i < NB) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) v[s][j] = lds[lpad((i + j * NB) * G + g)];
+            }
+        }
+    }
+
+    template <bool INV>
+    __device__ __forceinline__ static void twiddle(float2 (&v)[S][R], const float2 *__restrict__ tw, int tt)
+    {
+        if constexpr (P > 1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = tt + s * TF;
+                if (NB % TF == 0 || i < NB) {
+                    const int k = i % P;
+                    const float2 *t = tw + k * (R - 1);
+#pragma unroll
+                    for (int j = 1; j < R; ++j) v[s][j] = INV ? cmulc(v[s][j], t[j - 1]) : cmul(v[s][j], t[j - 1]);
+                }
+            }
+        }
+    }
+
+    template <bool INV>
+    __device__ __forceinline__ static void butterfly(float2 (&v)[S][R], int tt)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tt + s * TF;
+            if (NB % TF == 0 || i < NB) dftc<R, INV>(v[s]);
+        }
+    }
+
+    // outputs of butterfly i: element (i - k) R + k + j P, k = i mod P
+    __device__ __forceinline__ static void store(const float2 (&v)[S][R], float2 *lds, int tt, int g)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tt + s * TF;
+            if (NB % TF == 0 || i < NB) {
+                const int k = i % P;
+                const int base = (i - k) * R + k;
+#pragma unroll
+                for (int j = 0; j < R; ++j) lds[lpad((base + j * P) * G + g)] = v[s][j];
+            }
+        }
+    }
+};
+
+}  // namespace lp

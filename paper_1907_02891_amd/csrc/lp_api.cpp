@@ -135,6 +135,19 @@ void make_fft(int64_t n, lp::FftDesc *d, std::vector<float> *tw)
     if (tw->empty()) { tw->push_back(1.f); tw->push_back(0.f); }
 }
 
+// Twiddles of one pass of radix r after sub-transforms of length p:
+// exp(-2 pi i j k / (p r)) at k * (r - 1) + (j - 1), appended to *tw.
+void pass_table(int64_t p, int r, std::vector<float> *tw)
+{
+    for (int64_t k = 0; k < p; ++k)
+        for (int j = 1; j < r; ++j) {
+            double c, s;
+            exp_frac(j * k, p * r, &c, &s);
+            tw->push_back(static_cast<float>(c));
+            tw->push_back(static_cast<float>(-s));
+        }
+}
+
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 int ilog2(int64_t v)
@@ -164,8 +177,13 @@ struct lp_plan {
     // transforms and tables (host copies)
     lp::FftDesc fx, fy;
     std::vector<float> twx, twy, rtw;
+    // register-resident column stage (if the padded column length has one)
+    int col_spec = -1;
+    int variant = 0;  // 0: specialised kernels where available, 1: generic only
+    std::vector<float> twc;  // its four pass tables, concatenated
+    size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
     // workspace layout (byte offsets)
-    size_t off_w, off_kh, off_twx, off_twy, off_rtw, bytes;
+    size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, bytes;
     size_t scratch_bytes;
     // binding
     char *ws = nullptr;
@@ -195,7 +213,8 @@ void layout(lp_plan *p)
     p->off_twx = p->off_kh + align256(static_cast<size_t>(p->nblk) * p->py * C * 8);
     p->off_rtw = p->off_twx + align256(p->twx.size() * 4);
     p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
-    p->bytes = p->off_twy + align256(p->twy.size() * 4);
+    p->off_twc = p->off_twy + align256(p->twy.size() * 4);
+    p->bytes = p->off_twc + align256(std::max<size_t>(p->twc.size(), 2) * 4);
 }
 
 // Launch shape: C = columns per workgroup of the column stage (a power of
@@ -204,20 +223,16 @@ void layout(lp_plan *p)
 // >= min(ny, 256) workgroups).
 void choose_shape(lp_plan *p)
 {
-    int logc = 0;
-    for (int l = 6; l >= 0; --l) {
-        const int64_t C = int64_t{1} << l;
-        const int64_t nblk = (p->h + C - 1) / C;
-        if (p->py * C * 8 <= lp::kLdsBytes && nblk >= std::min<int64_t>(p->h, 512)) { logc = l; break; }
-    }
+    // Column-major intermediate (one column = one contiguous run of ny
+    // values); one column per workgroup of the column stage.
+    const int logc = 0;
     p->logc = logc;
-    p->nblk = (p->h + (int64_t{1} << logc) - 1) >> logc;
+    p->nblk = p->h;
     int logb = 0;
-    for (int l = 5; l >= 0; --l) {
+    for (int l = 4; l >= 0; --l) {
         const int64_t B = int64_t{1} << l;
         const int64_t groups = (p->ny + B - 1) / B;
-        if ((p->m + 1) * B * 8 <= lp::kLdsBytes && (B << logc) <= 32 &&
-            groups >= std::min<int64_t>(p->ny, 256)) { logb = l; break; }
+        if ((p->m + 1) * B * 8 <= lp::kLdsBytes && groups >= std::min<int64_t>(p->ny, 256)) { logb = l; break; }
     }
     p->logb = logb;
     p->t_cols = threads_for(p->py << logc);
@@ -243,6 +258,16 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     p->h = p->m + 1;
     make_fft(p->m, &p->fx, &p->twx);
     make_fft(p->py, &p->fy, &p->twy);
+    p->col_spec = lp::col_spec_index(static_cast<int>(py));
+    p->twc.clear();
+    if (p->col_spec >= 0) {
+        const lp::ColSpec c = lp::kColSpecs[p->col_spec];
+        const int tabs[4][2] = {{c.r0, c.r1}, {c.r0 * c.r1, c.r2}, {c.r2, c.r1}, {c.r2 * c.r1, c.r0}};
+        for (int t = 0; t < 4; ++t) {
+            p->twc_off[t] = p->twc.size() / 2;
+            pass_table(tabs[t][0], tabs[t][1], &p->twc);
+        }
+    }
     p->rtw.assign(2 * (p->m + 1), 0.f);
     for (int64_t k = 0; k <= p->m; ++k) {
         double c, s;
@@ -303,8 +328,22 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
     if ((e = lp::launch_rows_r2c(in, W, ra, p->t_rows, p->stream)) != hipSuccess)
         return fail_hip(e, "rows forward launch");
     if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
-    if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream)) != hipSuccess)
+    if (p->col_spec >= 0 && p->variant == 0) {
+        lp::ColRegArgs cr{};
+        const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
+        cr.ny = static_cast<int32_t>(p->ny);
+        cr.ku = ca.ku;
+        cr.kh = ca.kh;
+        cr.tw_f1 = twc + p->twc_off[0];
+        cr.tw_f2 = twc + p->twc_off[1];
+        cr.tw_i1 = twc + p->twc_off[2];
+        cr.tw_i2 = twc + p->twc_off[3];
+        if ((e = lp::launch_cols_reg(W, cr, static_cast<int>(p->py), static_cast<int>(p->h), p->form,
+                                     adjoint, p->stream)) != hipSuccess)
+            return fail_hip(e, "column stage launch");
+    } else if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream)) != hipSuccess) {
         return fail_hip(e, "column stage launch");
+    }
     if (rec && (e = hipEventRecord(ev[2], p->stream)) != hipSuccess) return fail_hip(e, who);
     if ((e = lp::launch_rows_c2r(W, out, ra, p->t_rows, p->stream)) != hipSuccess)
         return fail_hip(e, "rows inverse launch");
@@ -383,6 +422,22 @@ int lp_plan_get_padding(const lp_plan *p, int64_t *py, int64_t *px)
 
 size_t lp_plan_workspace_bytes(const lp_plan *p) { return p ? p->bytes : 0; }
 
+int lp_plan_set_kernels(lp_plan *p, int which)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (which != LP_KERNELS_AUTO && which != LP_KERNELS_GENERIC)
+        return fail(LP_E_INVALID, "unknown kernel family %d", which);
+    p->variant = which;
+    return LP_OK;
+}
+
+int lp_plan_kernels(const lp_plan *p)
+{
+    if (!p) return -1;
+    return (p->col_spec >= 0 && p->variant == 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
+}
+
 int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
 {
     clear_error();
@@ -411,9 +466,9 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
     p->bound = false;
     p->form = LP_FORM_NONE;
     struct { size_t off; const std::vector<float> *v; } up[] = {
-        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}};
+        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}, {p->off_twc, &p->twc}};
     for (auto &u : up)
-        if ((e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
+        if (!u.v->empty() && (e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
                                 p->stream)) != hipSuccess)
             return fail_hip(e, "twiddle upload");
     if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "twiddle upload");

@@ -73,3 +73,35 @@ hipError_t launch_spec_cols(const double2 *t1, int ky, int cy, int py, int ku, i
 hipError_t set_kernel_attributes();
 
 }  // namespace lp
+
+namespace lp {
+
+// Register-resident column stage: padded column length N = R0 * R1 * R2,
+// TF threads per column (one column per workgroup).
+struct ColSpec {
+    int n, tf, r0, r1, r2;
+};
+constexpr ColSpec kColSpecs[] = {
+    {5400, 360, 20, 18, 15},
+    {18432, 768, 32, 24, 24},
+    {2880, 240, 16, 12, 15},
+    {512, 64, 8, 8, 8},
+};
+
+struct ColRegArgs {
+    int32_t ny;          // stored rows per column
+    int32_t ku;          // stored spectrum rows per column (n or n/2+1)
+    const void *kh;      // column-major spectrum (float real quadrant or float2)
+    const float2 *tw_f1; // exp(-2 pi i j k / (R0 R1)),      k < R0,      1 <= j < R1
+    const float2 *tw_f2; // exp(-2 pi i j k / N),            k < R0 R1,   1 <= j < R2
+    const float2 *tw_i1; // exp(-2 pi i j k / (R2 R1)),      k < R2,      1 <= j < R1
+    const float2 *tw_i2; // exp(-2 pi i j k / N),            k < R2 R1,   1 <= j < R0
+};
+
+// Index of the specialisation for column length n, or -1.
+int col_spec_index(int n);
+size_t col_spec_lds_bytes(int n);
+hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int form, bool conj_k,
+                           hipStream_t s);
+
+}  // namespace lp

@@ -319,3 +319,178 @@ hipError_t set_kernel_attributes()
 }
 
 }  // namespace lp
+
+// ===================================================== register-resident columns
+#include "fft_reg.h"
+
+namespace lp {
+
+// One column per workgroup: forward transform (radices R0, R1, R2), spectrum
+// multiply in registers, inverse transform (radices R2, R1, R0; its first
+// pass consumes the forward's last-pass outputs straight from registers), and
+// only rows < ny read or written.  Column-major intermediate: column v is the
+// contiguous run W[v * ny .. v * ny + ny).
+template <int N, int TF, int R0, int R1, int R2, int FORM, bool CONJ>
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64) k_cols_reg(float2 *__restrict__ W, ColRegArgs a)
+{
+    extern __shared__ float2 lds[];
+    using F0 = RegPass<N, R0, 1, TF, 1>;
+    using F1 = RegPass<N, R1, R0, TF, 1>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1>;
+    using I0 = RegPass<N, R2, 1, TF, 1>;
+    using I1 = RegPass<N, R1, R2, TF, 1>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1>;
+    const int tt = threadIdx.x;
+    const bool act = tt < TF;
+    const int v = xcd_tile(blockIdx.x, gridDim.x);
+    const int ny = a.ny;
+    float2 *col = W + static_cast<int64_t>(v) * ny;
+
+    float2 x0[F0::S][R0];
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < F0::S; ++s) {
+            const int i = tt + s * TF;
+            if (F0::NB % TF == 0 || i < F0::NB) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) {
+                    const int n = i + j * F0::NB;
+                    x0[s][j] = (n < ny) ? col[n] : make_float2(0.f, 0.f);
+                }
+            }
+        }
+        F0::template butterfly<false>(x0, tt);
+        F0::store(x0, lds, tt, 0);
+    }
+    __syncthreads();
+    float2 x1[F1::S][R1];
+    if (act) {
+        F1::load(x1, lds, tt, 0);
+        F1::template twiddle<false>(x1, a.tw_f1, tt);
+        F1::template butterfly<false>(x1, tt);
+    }
+    __syncthreads();
+    if (act) F1::store(x1, lds, tt, 0);
+    __syncthreads();
+    float2 x2[F2::S][R2];
+    if (act) {
+        F2::load(x2, lds, tt, 0);
+        F2::template twiddle<false>(x2, a.tw_f2, tt);
+        F2::template butterfly<false>(x2, tt);
+        // Eq. 9: pixel-wise product with the kernel spectrum, element u = i + j NB
+#pragma unroll
+        for (int s = 0; s < F2::S; ++s) {
+            const int i = tt + s * TF;
+            if (F2::NB % TF == 0 || i < F2::NB) {
+                if constexpr (FORM == 1) {
+                    const float *kq = static_cast<const float *>(a.kh) + static_cast<int64_t>(v) * a.ku;
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int u = i + j * F2::NB;
+                        x2[s][j] = cscale(x2[s][j], kq[(2 * u <= N) ? u : N - u]);
+                    }
+                } else {
+                    const float2 *kc = static_cast<const float2 *>(a.kh) + static_cast<int64_t>(v) * N;
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const float2 k = kc[i + j * F2::NB];
+                        x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
+                    }
+                }
+            }
+        }
+        I0::template butterfly<true>(x2, tt);
+    }
+    __syncthreads();
+    if (act) I0::store(x2, lds, tt, 0);
+    __syncthreads();
+    float2 y1[I1::S][R1];
+    if (act) {
+        I1::load(y1, lds, tt, 0);
+        I1::template twiddle<true>(y1, a.tw_i1, tt);
+        I1::template butterfly<true>(y1, tt);
+    }
+    __syncthreads();
+    if (act) I1::store(y1, lds, tt, 0);
+    __syncthreads();
+    if (act) {
+        float2 y2[I2::S][R0];
+        I2::load(y2, lds, tt, 0);
+        I2::template twiddle<true>(y2, a.tw_i2, tt);
+        I2::template butterfly<true>(y2, tt);
+#pragma unroll
+        for (int s = 0; s < I2::S; ++s) {
+            const int i = tt + s * TF;
+            if (I2::NB % TF == 0 || i < I2::NB) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) {
+                    const int n = i + j * I2::NB;
+                    if (n < ny) col[n] = y2[s][j];
+                }
+            }
+        }
+    }
+}
+
+int col_spec_index(int n)
+{
+    for (int i = 0; i < static_cast<int>(sizeof kColSpecs / sizeof kColSpecs[0]); ++i)
+        if (kColSpecs[i].n == n) return i;
+    return -1;
+}
+
+size_t col_spec_lds_bytes(int n) { return static_cast<size_t>(lds_words(n)) * 8; }
+
+template <int I>
+static hipError_t launch_col_spec(float2 *W, const ColRegArgs &a, int ncols, int form, bool conj_k,
+                                  hipStream_t s)
+{
+    constexpr ColSpec c = kColSpecs[I];
+    const dim3 g(ncols), t(((c.tf + 63) / 64) * 64);
+    const size_t lds = col_spec_lds_bytes(c.n);
+    if (form == 1)
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 1, false>), g, t, lds, s, W, a);
+    else if (conj_k)
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, true>), g, t, lds, s, W, a);
+    else
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, false>), g, t, lds, s, W, a);
+    return hipGetLastError();
+}
+
+template <int I>
+static hipError_t set_col_spec_attr()
+{
+    constexpr ColSpec c = kColSpecs[I];
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 1, false>),
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, false>),
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, true>),
+    };
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int form, bool conj_k,
+                           hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e;
+        if ((e = set_col_spec_attr<0>()) != hipSuccess || (e = set_col_spec_attr<1>()) != hipSuccess ||
+            (e = set_col_spec_attr<2>()) != hipSuccess || (e = set_col_spec_attr<3>()) != hipSuccess)
+            return e;
+        attr = true;
+    }
+    switch (col_spec_index(n)) {
+        case 0: return launch_col_spec<0>(W, a, ncols, form, conj_k, s);
+        case 1: return launch_col_spec<1>(W, a, ncols, form, conj_k, s);
+        case 2: return launch_col_spec<2>(W, a, ncols, form, conj_k, s);
+        case 3: return launch_col_spec<3>(W, a, ncols, form, conj_k, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace lp

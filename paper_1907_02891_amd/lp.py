@@ -25,6 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 LP_OK, LP_E_INVALID, LP_E_SIZE, LP_E_STATE, LP_E_NOMEM, LP_E_DEVICE = 0, -1, -2, -3, -4, -5
 FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
+KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
 MAX_PY, MAX_PX = 20480, 40958
 
 _vp = ctypes.c_void_p
@@ -52,6 +53,8 @@ _SIGS = {
     "lp_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_stage_ms": ([_vp, _dp, ctypes.c_int, _ip], ctypes.c_int),
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
+    "lp_plan_set_kernels": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_kernels": ([_vp], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -194,6 +197,15 @@ class Plan:
                                ctypes.c_void_p(out.data_ptr())))
         return out
 
+    def set_kernels(self, which):
+        """KERNELS_AUTO (specialised column kernel where available) or
+        KERNELS_GENERIC."""
+        _check(_lib.lp_plan_set_kernels(self._p, int(which)))
+
+    @property
+    def kernels(self):
+        return int(_lib.lp_plan_kernels(self._p))
+
     def timing(self, enable=True):
         _check(_lib.lp_plan_timing(self._p, int(bool(enable))))
 
@@ -205,10 +217,11 @@ class Plan:
         return list(ms), calls.value
 
 
-def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None):
+def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO):
     """Plan + workspace + kernel spectrum in one call."""
     psf = np.asarray(psf)
     p = Plan(ny, nx, psf.shape[0], psf.shape[1], pitch_km, padding)
+    p.set_kernels(kernels)
     p.bind(device=device)
     p.set_kernel(psf)
     return p

@@ -196,3 +196,32 @@ def test_linearity_and_sum(lp, torch):
     assert oracle.rel_l2(S12, 2.0 * S1 + 0.5 * S2) <= 1e-6
     # zero margin >= (k-1)/2: the "same" window holds the whole sum
     assert S1.sum() == pytest.approx(R1.astype(np.float64).sum() * K.sum(), rel=1e-5)
+
+
+# ------------------------------------------- specialised register kernels --
+
+SPEC_CASES = [  # ny, nx, ky, kx, padding, symmetric
+    (200, 64, 9, 9, (512, 80), True), (300, 40, 11, 5, (512, 48), False),
+    (2870, 30, 11, 7, (2880, 36), True), (1000, 24, 101, 3, (2880, 30), False),
+    (4096, 16, 1201, 3, (5400, 18), True), (3500, 12, 801, 1, (5400, 12), False),
+]
+
+
+@pytest.mark.parametrize("case", SPEC_CASES, ids=[f"py{c[4][0]}-{c[0]}x{c[1]}{'s' if c[5] else 'g'}" for c in SPEC_CASES])
+def test_specialised_column_kernel(lp, torch, case):
+    """Columns of the specialised lengths (512, 2880, 5400) against the oracle
+    and against the generic LDS kernel, forward and adjoint."""
+    ny, nx, ky, kx, pad, sym = case
+    rng = np.random.default_rng(ny * 7 + nx)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    spec = lp.make_plan(K, ny, nx, padding=pad)
+    assert spec.kernels == lp.KERNELS_SPECIALISED
+    gen = lp.make_plan(K, ny, nx, padding=pad, kernels=lp.KERNELS_GENERIC)
+    assert gen.kernels == lp.KERNELS_GENERIC
+    x = torch.from_numpy(R).cuda()
+    a, b = spec.convolve(x).cpu().numpy(), gen.convolve(x).cpu().numpy()
+    assert_parity(a, oracle.conv_same(R, K), label=f"spec {case}")
+    assert oracle.rel_l2(a, b) <= 2 * TOL
+    g = spec.adjoint(x).cpu().numpy()
+    assert_parity(g, oracle.adjoint_same(R, K), label=f"spec adjoint {case}")

@@ -152,13 +152,14 @@ int lp_adjoint(lp_plan *plan, const float *grad_out, float *grad_in);
 int lp_plan_timing(lp_plan *plan, int enable);
 int lp_plan_stage_ms(lp_plan *plan, double *ms, int n, int *calls);
 
-/* Kernel family of the column stage.  LP_KERNELS_AUTO (default): a
- * register-resident kernel specialised at compile time for the padded column
- * length when the library has one (three large-radix passes, the spectrum
- * multiply in registers), else the generic LDS-staged kernel;
- * LP_KERNELS_GENERIC: always the generic one.  lp_plan_kernels reports which
- * family lp_convolve will run (LP_KERNELS_SPECIALISED or LP_KERNELS_GENERIC;
- * -1 for a NULL plan). */
+/* Kernel family of the three stages.  LP_KERNELS_AUTO (default): for each
+ * stage, a register-resident kernel specialised at compile time for the
+ * padded column length (column stage) or half row length (row stages) when
+ * the library has one -- three large-radix passes, the spectrum multiply and
+ * the real-to-complex split in registers -- else the generic LDS-staged
+ * kernel; LP_KERNELS_GENERIC: always the generic ones.  lp_plan_kernels
+ * reports LP_KERNELS_SPECIALISED if lp_convolve runs at least one specialised
+ * stage, else LP_KERNELS_GENERIC (-1 for a NULL plan). */
 enum { LP_KERNELS_AUTO = 0, LP_KERNELS_GENERIC = 1, LP_KERNELS_SPECIALISED = 2 };
 int lp_plan_set_kernels(lp_plan *plan, int which);
 int lp_plan_kernels(const lp_plan *plan);

@@ -182,8 +182,12 @@ struct lp_plan {
     int variant = 0;  // 0: specialised kernels where available, 1: generic only
     std::vector<float> twc;  // its four pass tables, concatenated
     size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
+    // register-resident row stages (if the half row length has one)
+    int row_spec = -1;
+    std::vector<float> twr;
+    size_t twr_off[4] = {0, 0, 0, 0};
     // workspace layout (byte offsets)
-    size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, bytes;
+    size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, off_twr, bytes;
     size_t scratch_bytes;
     // binding
     char *ws = nullptr;
@@ -214,7 +218,8 @@ void layout(lp_plan *p)
     p->off_rtw = p->off_twx + align256(p->twx.size() * 4);
     p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
     p->off_twc = p->off_twy + align256(p->twy.size() * 4);
-    p->bytes = p->off_twc + align256(std::max<size_t>(p->twc.size(), 2) * 4);
+    p->off_twr = p->off_twc + align256(std::max<size_t>(p->twc.size(), 2) * 4);
+    p->bytes = p->off_twr + align256(std::max<size_t>(p->twr.size(), 2) * 4);
 }
 
 // Launch shape: C = columns per workgroup of the column stage (a power of
@@ -266,6 +271,16 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
         for (int t = 0; t < 4; ++t) {
             p->twc_off[t] = p->twc.size() / 2;
             pass_table(tabs[t][0], tabs[t][1], &p->twc);
+        }
+    }
+    p->row_spec = lp::row_spec_index(static_cast<int>(p->m));
+    p->twr.clear();
+    if (p->row_spec >= 0) {
+        const lp::RowSpec c = lp::kRowSpecs[p->row_spec];
+        const int tabs[4][2] = {{c.r0, c.r1}, {c.r0 * c.r1, c.r2}, {c.r2, c.r1}, {c.r2 * c.r1, c.r0}};
+        for (int t = 0; t < 4; ++t) {
+            p->twr_off[t] = p->twr.size() / 2;
+            pass_table(tabs[t][0], tabs[t][1], &p->twr);
         }
     }
     p->rtw.assign(2 * (p->m + 1), 0.f);
@@ -325,8 +340,22 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
     float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
     const lp::RowArgs ra = row_args(p);
     const lp::ColArgs ca = col_args(p);
-    if ((e = lp::launch_rows_r2c(in, W, ra, p->t_rows, p->stream)) != hipSuccess)
-        return fail_hip(e, "rows forward launch");
+    const bool rspec = p->row_spec >= 0 && p->variant == 0;
+    lp::RowRegArgs rr{};
+    if (rspec) {
+        const float2 *twr = reinterpret_cast<const float2 *>(p->ws + p->off_twr);
+        rr.ny = static_cast<int32_t>(p->ny);
+        rr.nx = static_cast<int32_t>(p->nx);
+        rr.rtw = ra.rtw;
+        rr.tw_f1 = twr + p->twr_off[0];
+        rr.tw_f2 = twr + p->twr_off[1];
+        rr.tw_i1 = twr + p->twr_off[2];
+        rr.tw_i2 = twr + p->twr_off[3];
+        e = lp::launch_rows_r2c_reg(in, W, rr, p->row_spec, p->stream);
+    } else {
+        e = lp::launch_rows_r2c(in, W, ra, p->t_rows, p->stream);
+    }
+    if (e != hipSuccess) return fail_hip(e, "rows forward launch");
     if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
     if (p->col_spec >= 0 && p->variant == 0) {
         lp::ColRegArgs cr{};
@@ -345,8 +374,9 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
         return fail_hip(e, "column stage launch");
     }
     if (rec && (e = hipEventRecord(ev[2], p->stream)) != hipSuccess) return fail_hip(e, who);
-    if ((e = lp::launch_rows_c2r(W, out, ra, p->t_rows, p->stream)) != hipSuccess)
-        return fail_hip(e, "rows inverse launch");
+    e = rspec ? lp::launch_rows_c2r_reg(W, out, rr, p->row_spec, p->stream)
+              : lp::launch_rows_c2r(W, out, ra, p->t_rows, p->stream);
+    if (e != hipSuccess) return fail_hip(e, "rows inverse launch");
     if (rec) {
         if ((e = hipEventRecord(ev[3], p->stream)) != hipSuccess) return fail_hip(e, who);
         ++p->ev_calls;
@@ -435,7 +465,8 @@ int lp_plan_set_kernels(lp_plan *p, int which)
 int lp_plan_kernels(const lp_plan *p)
 {
     if (!p) return -1;
-    return (p->col_spec >= 0 && p->variant == 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
+    if (p->variant != 0) return LP_KERNELS_GENERIC;
+    return (p->col_spec >= 0 || p->row_spec >= 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
 }
 
 int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
@@ -443,7 +474,8 @@ int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
     clear_error();
     if (!p) return fail(LP_E_INVALID, "null plan");
     if (cols_per_group) *cols_per_group = 1 << p->logc;
-    if (rows_per_group) *rows_per_group = 1 << p->logb;
+    if (rows_per_group)
+        *rows_per_group = (p->row_spec >= 0 && p->variant == 0) ? lp::row_spec_rows(p->row_spec) : 1 << p->logb;
     return LP_OK;
 }
 
@@ -466,7 +498,8 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
     p->bound = false;
     p->form = LP_FORM_NONE;
     struct { size_t off; const std::vector<float> *v; } up[] = {
-        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}, {p->off_twc, &p->twc}};
+        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}, {p->off_twc, &p->twc},
+        {p->off_twr, &p->twr}};
     for (auto &u : up)
         if (!u.v->empty() && (e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
                                 p->stream)) != hipSuccess)

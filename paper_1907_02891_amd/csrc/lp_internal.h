@@ -105,3 +105,32 @@ hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int
                            hipStream_t s);
 
 }  // namespace lp
+
+namespace lp {
+
+// Register-resident row stages: half row length M = Px/2 = R0 * R1 * R2
+// (forward radix order; the inverse runs R2, R1, R0), TF threads per row,
+// B rows per workgroup.
+struct RowSpec {
+    int m, tf, r0, r1, r2, b;
+};
+constexpr RowSpec kRowSpecs[] = {
+    {2700, 128, 15, 15, 12, 2},
+    {9216, 384, 16, 24, 24, 1},
+    {1440, 128, 12, 12, 10, 2},
+    {256, 64, 8, 8, 4, 4},
+};
+
+struct RowRegArgs {
+    int32_t ny, nx;
+    const float2 *rtw;   // exp(-2 pi i k / Px), 0 <= k <= M
+    const float2 *tw_f1, *tw_f2, *tw_i1, *tw_i2;  // as in ColRegArgs, for length M
+};
+
+int row_spec_index(int m);
+size_t row_spec_lds_bytes(int idx);
+int row_spec_rows(int idx);
+hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s);
+hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s);
+
+}  // namespace lp

@@ -494,3 +494,300 @@ hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int
 }
 
 }  // namespace lp
+
+// ======================================================= register-resident rows
+namespace lp {
+
+// Row z[n] = x[2n] + i x[2n+1] of the zero-padded map (columns >= nx, rows
+// >= ny are zero).
+template <bool EVEN_NX>
+__device__ __forceinline__ float2 load_pair(const float *__restrict__ src, int n, int nx, bool rv)
+{
+    const int c0 = 2 * n;
+    if (!rv || c0 >= nx) return make_float2(0.f, 0.f);
+    if (EVEN_NX) return *reinterpret_cast<const float2 *>(src + c0);
+    return make_float2(src[c0], (c0 + 1 < nx) ? src[c0 + 1] : 0.f);
+}
+
+// X[k] = E + w^k O from Z[k] (z) and Z[M-k] (zp): E = (z + conj zp)/2,
+// O = -i (z - conj zp)/2.
+__device__ __forceinline__ float2 r2c_split(float2 z, float2 zp, float2 w)
+{
+    const float2 E = make_float2(0.5f * (z.x + zp.x), 0.5f * (z.y - zp.y));
+    const float2 O = make_float2(0.5f * (z.y + zp.y), -0.5f * (z.x - zp.x));
+    return cadd(E, cmul(O, w));
+}
+
+// Twice the spectrum of x[2n] + i x[2n+1] at k from X[k] (x) and X[M-k] (xp):
+// (x + conj xp) + i conj(w^k) (x - conj xp).
+__device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
+{
+    const float2 s = make_float2(x.x + xp.x, x.y - xp.y);
+    const float2 d = make_float2(x.x - xp.x, x.y + xp.y);
+    const float2 wd = cmulc(d, w);
+    return make_float2(s.x - wd.y, s.y + wd.x);
+}
+
+// Forward rows.  Passes R0, R1 in the usual thread mapping; the last pass
+// (radix R2, NB = M/R2 butterflies) gives thread tt the butterflies tt and
+// NB - tt, so that it holds both Z[k] and Z[M-k] for every k it produced and
+// the real-to-complex split happens in registers.  Column-major output:
+// X[k] of row r at W[k * ny + r].
+template <int M, int TF, int R0, int R1, int R2, int B, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B) k_rows_r2c_reg(const float *__restrict__ Rm,
+                                                        float2 *__restrict__ W, RowRegArgs a)
+{
+    extern __shared__ float2 lds[];
+    using F0 = RegPass<M, R0, 1, TF, B>;
+    using F1 = RegPass<M, R1, R0, TF, B>;
+    constexpr int NB = M / R2;
+    static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
+    const int tid = threadIdx.x, b = tid % B, tt = tid / B;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * B + b;
+    const bool rv = row < a.ny;
+    const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
+
+    {
+        float2 x0[F0::S][R0];
+#pragma unroll
+        for (int s = 0; s < F0::S; ++s) {
+            const int i = tt + s * TF;
+            if (F0::NB % TF == 0 || i < F0::NB) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) x0[s][j] = load_pair<EVEN_NX>(src, i + j * F0::NB, a.nx, rv);
+            }
+        }
+        F0::template butterfly<false>(x0, tt);
+        F0::store(x0, lds, tt, b);
+    }
+    __syncthreads();
+    {
+        float2 x1[F1::S][R1];
+        F1::load(x1, lds, tt, b);
+        F1::template twiddle<false>(x1, a.tw_f1, tt);
+        F1::template butterfly<false>(x1, tt);
+        __syncthreads();
+        F1::store(x1, lds, tt, b);
+    }
+    __syncthreads();
+    if (tt > NB / 2) return;
+    const int i1 = tt, i2 = NB - tt;
+    const bool two = (i2 != i1) && (i2 < NB);
+    float2 z1[R2], z2[R2];
+#pragma unroll
+    for (int j = 0; j < R2; ++j) z1[j] = lds[lpad((i1 + j * NB) * B + b)];
+    if (i1 > 0) {
+#pragma unroll
+        for (int j = 1; j < R2; ++j) z1[j] = cmul(z1[j], a.tw_f2[i1 * (R2 - 1) + j - 1]);
+    }
+    dftc<R2, false>(z1);
+    if (two) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) z2[j] = cmul(lds[lpad((i2 + j * NB) * B + b)], j ? a.tw_f2[i2 * (R2 - 1) + j - 1] : make_float2(1.f, 0.f));
+        dftc<R2, false>(z2);
+    }
+    if (!rv) return;
+    float2 *dst = W + row;
+    const int64_t ny = a.ny;
+    if (i1 == 0) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+            const int k = j * NB;
+            dst[k * ny] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+        }
+        dst[static_cast<int64_t>(M) * ny] = r2c_split(z1[0], z1[0], a.rtw[M]);
+    } else if (!two) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+            const int k = i1 + j * NB;
+            dst[k * ny] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+            const int k1 = i1 + j * NB, k2 = i2 + j * NB;
+            dst[k1 * ny] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
+            dst[k2 * ny] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+        }
+    }
+}
+
+// Inverse rows: the first pass (radix R2, NB = M/R2) pairs butterflies tt and
+// NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
+// and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).
+template <int M, int TF, int R0, int R1, int R2, int B, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B) k_rows_c2r_reg(const float2 *__restrict__ W,
+                                                        float *__restrict__ Sm, RowRegArgs a)
+{
+    extern __shared__ float2 lds[];
+    using I1 = RegPass<M, R1, R2, TF, B>;
+    using I2 = RegPass<M, R0, R2 * R1, TF, B>;
+    constexpr int NB = M / R2;
+    static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
+    const int tid = threadIdx.x, b = tid % B, tt = tid / B;
+    const int row = xcd_tile(blockIdx.x, gridDim.x) * B + b;
+    const bool rv = row < a.ny;
+    const int64_t ny = a.ny;
+
+    if (tt <= NB / 2) {
+        const int i1 = tt, i2 = NB - tt;
+        const bool two = (i2 != i1) && (i2 < NB);
+        const float2 *src = W + (rv ? row : 0);
+        const float2 zero = make_float2(0.f, 0.f);
+        float2 xa[R2], xb[R2];
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+            xa[j] = rv ? src[static_cast<int64_t>(i1 + j * NB) * ny] : zero;
+            xb[j] = (rv && two) ? src[static_cast<int64_t>(i2 + j * NB) * ny] : zero;
+        }
+        float2 za[R2], zb[R2];
+        if (i1 == 0) {
+            const float2 xm = rv ? src[static_cast<int64_t>(M) * ny] : zero;
+#pragma unroll
+            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], j ? xa[R2 - j] : xm, a.rtw[j * NB]);
+        } else if (!two) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], xa[R2 - 1 - j], a.rtw[i1 + j * NB]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) {
+                za[j] = c2r_merge(xa[j], xb[R2 - 1 - j], a.rtw[i1 + j * NB]);
+                zb[j] = c2r_merge(xb[j], xa[R2 - 1 - j], a.rtw[i2 + j * NB]);
+            }
+        }
+        dftc<R2, true>(za);
+#pragma unroll
+        for (int j = 0; j < R2; ++j) lds[lpad((i1 * R2 + j) * B + b)] = za[j];
+        if (two) {
+            dftc<R2, true>(zb);
+#pragma unroll
+            for (int j = 0; j < R2; ++j) lds[lpad((i2 * R2 + j) * B + b)] = zb[j];
+        }
+    }
+    __syncthreads();
+    {
+        float2 y1[I1::S][R1];
+        I1::load(y1, lds, tt, b);
+        I1::template twiddle<true>(y1, a.tw_i1, tt);
+        I1::template butterfly<true>(y1, tt);
+        __syncthreads();
+        I1::store(y1, lds, tt, b);
+    }
+    __syncthreads();
+    float2 y2[I2::S][R0];
+    I2::load(y2, lds, tt, b);
+    I2::template twiddle<true>(y2, a.tw_i2, tt);
+    I2::template butterfly<true>(y2, tt);
+    if (!rv) return;
+    float *dst = Sm + static_cast<int64_t>(row) * a.nx;
+#pragma unroll
+    for (int s = 0; s < I2::S; ++s) {
+        const int i = tt + s * TF;
+        if (I2::NB % TF == 0 || i < I2::NB) {
+#pragma unroll
+            for (int j = 0; j < R0; ++j) {
+                const int c0 = 2 * (i + j * I2::NB);
+                if (EVEN_NX) {
+                    if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
+                } else {
+                    if (c0 < a.nx) dst[c0] = y2[s][j].x;
+                    if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
+                }
+            }
+        }
+    }
+}
+
+int row_spec_index(int m)
+{
+    for (int i = 0; i < static_cast<int>(sizeof kRowSpecs / sizeof kRowSpecs[0]); ++i)
+        if (kRowSpecs[i].m == m) return i;
+    return -1;
+}
+
+size_t row_spec_lds_bytes(int idx)
+{
+    return static_cast<size_t>(lds_words(kRowSpecs[idx].m * kRowSpecs[idx].b)) * 8;
+}
+
+int row_spec_rows(int idx) { return kRowSpecs[idx].b; }
+
+template <int I, bool FWD, bool EVEN>
+static const void *row_fn()
+{
+    constexpr RowSpec c = kRowSpecs[I];
+    if constexpr (FWD)
+        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, EVEN>);
+    else
+        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, EVEN>);
+}
+
+template <int I>
+static hipError_t set_row_spec_attr()
+{
+    const void *fns[] = {row_fn<I, true, true>(), row_fn<I, true, false>(), row_fn<I, false, true>(),
+                         row_fn<I, false, false>()};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+static hipError_t row_attrs()
+{
+    static bool attr = false;
+    if (attr) return hipSuccess;
+    hipError_t e;
+    if ((e = set_row_spec_attr<0>()) != hipSuccess || (e = set_row_spec_attr<1>()) != hipSuccess ||
+        (e = set_row_spec_attr<2>()) != hipSuccess || (e = set_row_spec_attr<3>()) != hipSuccess)
+        return e;
+    attr = true;
+    return hipSuccess;
+}
+
+template <int I>
+static hipError_t launch_row_spec(const void *in, void *out, const RowRegArgs &a, bool fwd, hipStream_t s)
+{
+    constexpr RowSpec c = kRowSpecs[I];
+    const dim3 g((a.ny + c.b - 1) / c.b), t(c.tf * c.b);
+    const size_t lds = row_spec_lds_bytes(I);
+    const bool even = (a.nx % 2) == 0;
+    if (fwd) {
+        const float *R = static_cast<const float *>(in);
+        float2 *W = static_cast<float2 *>(out);
+        if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, true>), g, t, lds, s, R, W, a);
+        else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, false>), g, t, lds, s, R, W, a);
+    } else {
+        const float2 *W = static_cast<const float2 *>(in);
+        float *S = static_cast<float *>(out);
+        if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, true>), g, t, lds, s, W, S, a);
+        else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, false>), g, t, lds, s, W, S, a);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_row_any(const void *in, void *out, const RowRegArgs &a, int idx, bool fwd, hipStream_t s)
+{
+    hipError_t e = row_attrs();
+    if (e != hipSuccess) return e;
+    switch (idx) {
+        case 0: return launch_row_spec<0>(in, out, a, fwd, s);
+        case 1: return launch_row_spec<1>(in, out, a, fwd, s);
+        case 2: return launch_row_spec<2>(in, out, a, fwd, s);
+        case 3: return launch_row_spec<3>(in, out, a, fwd, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s)
+{
+    return launch_row_any(R, W, a, idx, true, s);
+}
+
+hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s)
+{
+    return launch_row_any(W, S, a, idx, false, s);
+}
+
+}  // namespace lp

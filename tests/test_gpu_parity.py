@@ -225,3 +225,29 @@ def test_specialised_column_kernel(lp, torch, case):
     assert oracle.rel_l2(a, b) <= 2 * TOL
     g = spec.adjoint(x).cpu().numpy()
     assert_parity(g, oracle.adjoint_same(R, K), label=f"spec adjoint {case}")
+
+
+ROW_CASES = [  # ny, nx, ky, kx, padding, symmetric
+    (9, 4099, 3, 101, (12, 5400), False), (10, 4096, 5, 1201, (15, 5400), True),
+    (7, 2048, 3, 801, (9, 2880), True), (6, 2871, 1, 9, (6, 2880), False),
+    (33, 257, 5, 101, (40, 512), True), (30, 500, 3, 13, (32, 512), False),
+]
+
+
+@pytest.mark.parametrize("case", ROW_CASES, ids=[f"px{c[4][1]}-{c[0]}x{c[1]}{'s' if c[5] else 'g'}" for c in ROW_CASES])
+def test_specialised_row_kernels(lp, torch, case):
+    """Rows of the specialised half lengths (256, 1440, 2700), odd and even
+    widths, row counts not a multiple of the rows per workgroup."""
+    ny, nx, ky, kx, pad, sym = case
+    rng = np.random.default_rng(ny * 13 + nx)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    spec = lp.make_plan(K, ny, nx, padding=pad)
+    assert spec.kernels == lp.KERNELS_SPECIALISED
+    gen = lp.make_plan(K, ny, nx, padding=pad, kernels=lp.KERNELS_GENERIC)
+    x = torch.from_numpy(R).cuda()
+    a, b = spec.convolve(x).cpu().numpy(), gen.convolve(x).cpu().numpy()
+    assert_parity(a, oracle.conv_same(R, K), label=f"rows {case}")
+    assert oracle.rel_l2(a, b) <= 2 * TOL
+    g = spec.adjoint(x).cpu().numpy()
+    assert_parity(g, oracle.adjoint_same(R, K), label=f"rows adjoint {case}")

@@ -143,28 +143,51 @@ __device__ __forceinline__ void dftc(float2 *x)
     }
 }
 
-// LDS word index with one pad word per 32.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 5); }
-constexpr int lds_words(int n) { return n + (n >> 5) + 1; }
+// ---------------------------------------------------------------- LDS layout
+// Each LDS exchange buffer has one of two layouts, chosen so that both the
+// writing and the reading pass address it as (per-butterfly base) + (compile-
+// time offset) * j -- one address computation per butterfly, immediate
+// offsets for its R elements:
+//   L == 0: natural, element n at word n;
+//   L == Rw > 0 (written by a first pass of radix Rw, whose butterfly i
+//           writes elements i*Rw + j): element n at (n / Rw) * pitch(Rw) +
+//           n % Rw with an odd row pitch, so that the stride-Rw writes of
+//           consecutive lanes fall in different banks.
+// With G interleaved transforms, word w of transform g is at w * G + g.
+constexpr int lds_pitch(int rw) { return rw | 1; }
+constexpr int lds_words(int n, int rw) { return rw ? (n / rw) * lds_pitch(rw) : n; }
 
 // One pass of radix R over a length-N transform, with P = product of the
-// radices of earlier passes; G interleaved transforms per workgroup
-// (element n of transform g at LDS word lpad(n * G + g)); thread (tt, g) with
-// tt in [0, TF) takes butterflies i = tt + s * TF.
-template <int N, int R, int P, int TF, int G>
+// radices of earlier passes; G interleaved transforms per workgroup; thread
+// (tt, g), tt in [0, TF), takes butterflies i = tt + s * TF.  LIN / LOUT are
+// the layouts of the buffer it reads / writes (LOUT must be R when P == 1
+// and 0 otherwise).
+template <int N, int R, int P, int TF, int G, int LIN>
 struct RegPass {
     static constexpr int NB = N / R;
     static constexpr int S = (NB + TF - 1) / TF;
+    static constexpr int LOUT = (P == 1) ? R : 0;
+    static_assert(LIN == 0 || NB % LIN == 0, "input layout stride");
 
-    // inputs of butterfly i: element i + j * NB
+    __device__ __forceinline__ static bool valid(int i) { return NB % TF == 0 || i < NB; }
+
+    // inputs of butterfly i: elements i + j * NB
     __device__ __forceinline__ static void load(float2 (&v)[S][R], const float2 *lds, int tt, int g)
     {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int i = tt + s * TF;
-            if (NB % TF == 0 || i < NB) {
+            if (valid(i)) {
+                if constexpr (LIN == 0) {
+                    const float2 *q = lds + i * G + g;
 #pragma unroll
-                for (int j = 0; j < R; ++j) v[s][j] = lds[lpad((i + j * NB) * G + g)];
+                    for (int j = 0; j < R; ++j) v[s][j] = q[j * NB * G];
+                } else {
+                    constexpr int PITCH = lds_pitch(LIN);
+                    const float2 *q = lds + ((i / LIN) * PITCH + i % LIN) * G + g;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) v[s][j] = q[j * (NB / LIN) * PITCH * G];
+                }
             }
         }
     }
@@ -176,9 +199,8 @@ struct RegPass {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int i = tt + s * TF;
-                if (NB % TF == 0 || i < NB) {
-                    const int k = i % P;
-                    const float2 *t = tw + k * (R - 1);
+                if (valid(i)) {
+                    const float2 *t = tw + (i % P) * (R - 1);
 #pragma unroll
                     for (int j = 1; j < R; ++j) v[s][j] = INV ? cmulc(v[s][j], t[j - 1]) : cmul(v[s][j], t[j - 1]);
                 }
@@ -190,10 +212,8 @@ struct RegPass {
     __device__ __forceinline__ static void butterfly(float2 (&v)[S][R], int tt)
     {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int i = tt + s * TF;
-            if (NB % TF == 0 || i < NB) dftc<R, INV>(v[s]);
-        }
+        for (int s = 0; s < S; ++s)
+            if (valid(tt + s * TF)) dftc<R, INV>(v[s]);
     }
 
     // outputs of butterfly i: element (i - k) R + k + j P, k = i mod P
@@ -202,11 +222,17 @@ struct RegPass {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int i = tt + s * TF;
-            if (NB % TF == 0 || i < NB) {
-                const int k = i % P;
-                const int base = (i - k) * R + k;
+            if (valid(i)) {
+                if constexpr (P == 1) {
+                    float2 *q = lds + i * lds_pitch(R) * G + g;
 #pragma unroll
-                for (int j = 0; j < R; ++j) lds[lpad((base + j * P) * G + g)] = v[s][j];
+                    for (int j = 0; j < R; ++j) q[j * G] = v[s][j];
+                } else {
+                    const int k = i % P;
+                    float2 *q = lds + ((i - k) * R + k) * G + g;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) q[j * P * G] = v[s][j];
+                }
             }
         }
     }

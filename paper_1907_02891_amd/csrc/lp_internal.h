@@ -78,14 +78,15 @@ namespace lp {
 
 // Register-resident column stage: padded column length N = R0 * R1 * R2,
 // TF threads per column (one column per workgroup).
+// occ: minimum waves per SIMD asked of the register allocator (0: none).
 struct ColSpec {
-    int n, tf, r0, r1, r2;
+    int n, tf, r0, r1, r2, occ;
 };
 constexpr ColSpec kColSpecs[] = {
-    {5400, 360, 20, 18, 15},
-    {18432, 768, 32, 24, 24},
-    {2880, 240, 16, 12, 15},
-    {512, 64, 8, 8, 8},
+    {5400, 360, 20, 18, 15, 5},
+    {18432, 768, 32, 24, 24, 0},
+    {2880, 240, 16, 12, 15, 0},
+    {512, 64, 8, 8, 8, 0},
 };
 
 struct ColRegArgs {
@@ -112,13 +113,13 @@ namespace lp {
 // (forward radix order; the inverse runs R2, R1, R0), TF threads per row,
 // B rows per workgroup.
 struct RowSpec {
-    int m, tf, r0, r1, r2, b;
+    int m, tf, r0, r1, r2, b, occ;
 };
 constexpr RowSpec kRowSpecs[] = {
-    {2700, 128, 15, 15, 12, 2},
-    {9216, 384, 16, 24, 24, 1},
-    {1440, 128, 12, 12, 10, 2},
-    {256, 64, 8, 8, 4, 4},
+    {2700, 128, 15, 15, 12, 2, 0},
+    {9216, 384, 16, 24, 24, 1, 0},
+    {1440, 128, 12, 12, 10, 2, 0},
+    {256, 64, 8, 8, 4, 4, 0},
 };
 
 struct RowRegArgs {

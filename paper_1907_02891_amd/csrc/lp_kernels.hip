@@ -330,16 +330,16 @@ namespace lp {
 // pass consumes the forward's last-pass outputs straight from registers), and
 // only rows < ny read or written.  Column-major intermediate: column v is the
 // contiguous run W[v * ny .. v * ny + ny).
-template <int N, int TF, int R0, int R1, int R2, int FORM, bool CONJ>
-__global__ void __launch_bounds__(((TF + 63) / 64) * 64) k_cols_reg(float2 *__restrict__ W, ColRegArgs a)
+template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ>
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a)
 {
     extern __shared__ float2 lds[];
-    using F0 = RegPass<N, R0, 1, TF, 1>;
-    using F1 = RegPass<N, R1, R0, TF, 1>;
-    using F2 = RegPass<N, R2, R0 * R1, TF, 1>;
-    using I0 = RegPass<N, R2, 1, TF, 1>;
-    using I1 = RegPass<N, R1, R2, TF, 1>;
-    using I2 = RegPass<N, R0, R2 * R1, TF, 1>;
+    using F0 = RegPass<N, R0, 1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using I0 = RegPass<N, R2, 1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
     const int tt = threadIdx.x;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
@@ -439,7 +439,17 @@ int col_spec_index(int n)
     return -1;
 }
 
-size_t col_spec_lds_bytes(int n) { return static_cast<size_t>(lds_words(n)) * 8; }
+static constexpr int xchg_words(int n, int r0, int r2)
+{
+    const int a = lds_words(n, r0), c = lds_words(n, r2);
+    return (a > c ? a : c) > n ? (a > c ? a : c) : n;
+}
+
+size_t col_spec_lds_bytes(int n)
+{
+    const int i = col_spec_index(n);
+    return static_cast<size_t>(xchg_words(n, kColSpecs[i].r0, kColSpecs[i].r2)) * 8;
+}
 
 template <int I>
 static hipError_t launch_col_spec(float2 *W, const ColRegArgs &a, int ncols, int form, bool conj_k,
@@ -449,11 +459,11 @@ static hipError_t launch_col_spec(float2 *W, const ColRegArgs &a, int ncols, int
     const dim3 g(ncols), t(((c.tf + 63) / 64) * 64);
     const size_t lds = col_spec_lds_bytes(c.n);
     if (form == 1)
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 1, false>), g, t, lds, s, W, a);
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a);
     else if (conj_k)
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, true>), g, t, lds, s, W, a);
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a);
     else
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, false>), g, t, lds, s, W, a);
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a);
     return hipGetLastError();
 }
 
@@ -462,9 +472,9 @@ static hipError_t set_col_spec_attr()
 {
     constexpr ColSpec c = kColSpecs[I];
     const void *fns[] = {
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 1, false>),
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, false>),
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, 2, true>),
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>),
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>),
+        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>),
     };
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
@@ -533,13 +543,13 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // NB - tt, so that it holds both Z[k] and Z[M-k] for every k it produced and
 // the real-to-complex split happens in registers.  Column-major output:
 // X[k] of row r at W[k * ny + r].
-template <int M, int TF, int R0, int R1, int R2, int B, bool EVEN_NX>
-__global__ void __launch_bounds__(TF * B) k_rows_r2c_reg(const float *__restrict__ Rm,
-                                                        float2 *__restrict__ W, RowRegArgs a)
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__restrict__ Rm,
+                                                             float2 *__restrict__ W, RowRegArgs a)
 {
     extern __shared__ float2 lds[];
-    using F0 = RegPass<M, R0, 1, TF, B>;
-    using F1 = RegPass<M, R1, R0, TF, B>;
+    using F0 = RegPass<M, R0, 1, TF, B, 0>;
+    using F1 = RegPass<M, R1, R0, TF, B, R0>;
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     const int tid = threadIdx.x, b = tid % B, tt = tid / B;
@@ -575,7 +585,7 @@ __global__ void __launch_bounds__(TF * B) k_rows_r2c_reg(const float *__restrict
     const bool two = (i2 != i1) && (i2 < NB);
     float2 z1[R2], z2[R2];
 #pragma unroll
-    for (int j = 0; j < R2; ++j) z1[j] = lds[lpad((i1 + j * NB) * B + b)];
+    for (int j = 0; j < R2; ++j) z1[j] = lds[(i1 + j * NB) * B + b];
     if (i1 > 0) {
 #pragma unroll
         for (int j = 1; j < R2; ++j) z1[j] = cmul(z1[j], a.tw_f2[i1 * (R2 - 1) + j - 1]);
@@ -583,7 +593,9 @@ __global__ void __launch_bounds__(TF * B) k_rows_r2c_reg(const float *__restrict
     dftc<R2, false>(z1);
     if (two) {
 #pragma unroll
-        for (int j = 0; j < R2; ++j) z2[j] = cmul(lds[lpad((i2 + j * NB) * B + b)], j ? a.tw_f2[i2 * (R2 - 1) + j - 1] : make_float2(1.f, 0.f));
+        for (int j = 0; j < R2; ++j) z2[j] = lds[(i2 + j * NB) * B + b];
+#pragma unroll
+        for (int j = 1; j < R2; ++j) z2[j] = cmul(z2[j], a.tw_f2[i2 * (R2 - 1) + j - 1]);
         dftc<R2, false>(z2);
     }
     if (!rv) return;
@@ -615,13 +627,13 @@ __global__ void __launch_bounds__(TF * B) k_rows_r2c_reg(const float *__restrict
 // Inverse rows: the first pass (radix R2, NB = M/R2) pairs butterflies tt and
 // NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
 // and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).
-template <int M, int TF, int R0, int R1, int R2, int B, bool EVEN_NX>
-__global__ void __launch_bounds__(TF * B) k_rows_c2r_reg(const float2 *__restrict__ W,
-                                                        float *__restrict__ Sm, RowRegArgs a)
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
+                                                             float *__restrict__ Sm, RowRegArgs a)
 {
     extern __shared__ float2 lds[];
-    using I1 = RegPass<M, R1, R2, TF, B>;
-    using I2 = RegPass<M, R0, R2 * R1, TF, B>;
+    using I1 = RegPass<M, R1, R2, TF, B, R2>;
+    using I2 = RegPass<M, R0, R2 * R1, TF, B, 0>;
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     const int tid = threadIdx.x, b = tid % B, tt = tid / B;
@@ -657,11 +669,11 @@ __global__ void __launch_bounds__(TF * B) k_rows_c2r_reg(const float2 *__restric
         }
         dftc<R2, true>(za);
 #pragma unroll
-        for (int j = 0; j < R2; ++j) lds[lpad((i1 * R2 + j) * B + b)] = za[j];
+        for (int j = 0; j < R2; ++j) lds[(i1 * lds_pitch(R2) + j) * B + b] = za[j];
         if (two) {
             dftc<R2, true>(zb);
 #pragma unroll
-            for (int j = 0; j < R2; ++j) lds[lpad((i2 * R2 + j) * B + b)] = zb[j];
+            for (int j = 0; j < R2; ++j) lds[(i2 * lds_pitch(R2) + j) * B + b] = zb[j];
         }
     }
     __syncthreads();
@@ -707,7 +719,8 @@ int row_spec_index(int m)
 
 size_t row_spec_lds_bytes(int idx)
 {
-    return static_cast<size_t>(lds_words(kRowSpecs[idx].m * kRowSpecs[idx].b)) * 8;
+    const RowSpec &c = kRowSpecs[idx];
+    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * 8;
 }
 
 int row_spec_rows(int idx) { return kRowSpecs[idx].b; }
@@ -717,9 +730,9 @@ static const void *row_fn()
 {
     constexpr RowSpec c = kRowSpecs[I];
     if constexpr (FWD)
-        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
     else
-        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
 }
 
 template <int I>
@@ -756,13 +769,13 @@ static hipError_t launch_row_spec(const void *in, void *out, const RowRegArgs &a
     if (fwd) {
         const float *R = static_cast<const float *>(in);
         float2 *W = static_cast<float2 *>(out);
-        if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, true>), g, t, lds, s, R, W, a);
-        else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, false>), g, t, lds, s, R, W, a);
+        if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, R, W, a);
+        else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, R, W, a);
     } else {
         const float2 *W = static_cast<const float2 *>(in);
         float *S = static_cast<float *>(out);
-        if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, true>), g, t, lds, s, W, S, a);
-        else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, false>), g, t, lds, s, W, S, a);
+        if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, W, S, a);
+        else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, W, S, a);
     }
     return hipGetLastError();
 }

@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--check", type=int, default=256, help="sampled parity pixels (0: off)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (variant 0 of each stage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte calibration)")
     args = ap.parse_args()
@@ -142,6 +143,12 @@ def main():
 
     x = torch.from_numpy(R).to(dev)
     y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    tuning = None
+    if not args.no_tune:
+        from paper_1907_02891_amd import tune
+        tuning = tune.autotune(plan, x, y, use_cache=False)
+    t_tune = time.perf_counter() - t0
     for _ in range(args.warmup):
         plan.convolve(x, out=y)
     torch.cuda.synchronize()
@@ -193,7 +200,11 @@ def main():
                  "model_frac": round(path_b / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "wall_s": round(wall, 4)},
         "setup_s": {"inputs": round(t_gen, 2), "plan_bind": round(t_plan, 3),
-                    "kernel_spectrum": round(t_spec, 3)},
+                    "kernel_spectrum": round(t_spec, 3), "autotune": round(t_tune, 3)},
+        "variants": {lp_stage: {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
+                                "tried_ms": [round(t, 5) for t in (tuning or {}).get(lp_stage, {}).get("all", [])]}
+                     for lp_stage, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS))
+                     if plan.variant_count(st) > 0},
         "kernel_source": src_hash,
     }
 

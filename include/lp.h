@@ -164,6 +164,22 @@ enum { LP_KERNELS_AUTO = 0, LP_KERNELS_GENERIC = 1, LP_KERNELS_SPECIALISED = 2 }
 int lp_plan_set_kernels(lp_plan *plan, int which);
 int lp_plan_kernels(const lp_plan *plan);
 
+/* Variants (autotuning).  The library holds several compile-time
+ * specialisations for some lengths (different radix orders, threads per
+ * transform, transforms per workgroup, persistence with register prefetch);
+ * a plan starts on variant 0 of each stage.  lp_plan_variant_count: how many
+ * exist for the plan's padded size (0: none, the generic kernel runs).
+ * lp_plan_set_variant may be called at any time (after lp_plan_bind it
+ * re-uploads the stage's twiddle tables and synchronises the stream).
+ * lp_plan_variant_info writes up to n of {R0, R1, R2, threads per transform,
+ * transforms per workgroup, min waves per SIMD, tiles per workgroup (0: a
+ * persistent loop; always 1 for the column stage), length}. */
+enum { LP_STAGE_ROWS = 0, LP_STAGE_COLUMNS = 1 };
+int lp_plan_variant_count(const lp_plan *plan, int stage);
+int lp_plan_get_variant(const lp_plan *plan, int stage);
+int lp_plan_set_variant(lp_plan *plan, int stage, int k);
+int lp_plan_variant_info(const lp_plan *plan, int stage, int k, int *info, int n);
+
 /* Launch shape the plan chose (host pointers, any may be NULL): columns per
  * workgroup of the column stage, rows per workgroup of the row stages. */
 int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);

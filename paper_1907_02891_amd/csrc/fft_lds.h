@@ -201,6 +201,15 @@ __device__ void lds_fft(float2 *buf, const FftDesc &d, int logb, const float2 *_
     }
 }
 
+// The same value in a register the optimiser cannot see through: index
+// arithmetic derived from it inside a loop is recomputed per iteration instead
+// of being hoisted into registers that stay live across the whole loop.
+__device__ __forceinline__ int opaque_v(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Workgroup index remap so that consecutive logical tiles run on the same XCD
 // (the hardware deals workgroups round-robin over the 8 XCDs, each with its
 // own L2): logical = xcd * q + min(xcd, r) + (b / 8), a bijection on [0, G).

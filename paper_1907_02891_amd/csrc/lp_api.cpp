@@ -150,6 +150,24 @@ void pass_table(int64_t p, int r, std::vector<float> *tw)
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
+// Complex entries of the four pass tables of a three-pass specialisation:
+// forward passes (R0, R1, R2) and inverse passes (R2, R1, R0).
+size_t spec_table_len(int r0, int r1, int r2)
+{
+    return static_cast<size_t>(r0) * (r1 - 1) + static_cast<size_t>(r0) * r1 * (r2 - 1) +
+           static_cast<size_t>(r2) * (r1 - 1) + static_cast<size_t>(r2) * r1 * (r0 - 1);
+}
+
+void spec_tables(int r0, int r1, int r2, std::vector<float> *tw, size_t off[4])
+{
+    const int tabs[4][2] = {{r0, r1}, {r0 * r1, r2}, {r2, r1}, {r2 * r1, r0}};
+    tw->clear();
+    for (int t = 0; t < 4; ++t) {
+        off[t] = tw->size() / 2;
+        pass_table(tabs[t][0], tabs[t][1], tw);
+    }
+}
+
 int ilog2(int64_t v)
 {
     int l = 0;
@@ -179,6 +197,8 @@ struct lp_plan {
     std::vector<float> twx, twy, rtw;
     // register-resident column stage (if the padded column length has one)
     int col_spec = -1;
+    int col_variant = 0, row_variant = 0;  // k-th specialisation of each length
+    size_t twc_max = 2, twr_max = 2;       // table floats reserved (largest variant)
     int variant = 0;  // 0: specialised kernels where available, 1: generic only
     std::vector<float> twc;  // its four pass tables, concatenated
     size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
@@ -218,8 +238,8 @@ void layout(lp_plan *p)
     p->off_rtw = p->off_twx + align256(p->twx.size() * 4);
     p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
     p->off_twc = p->off_twy + align256(p->twy.size() * 4);
-    p->off_twr = p->off_twc + align256(std::max<size_t>(p->twc.size(), 2) * 4);
-    p->bytes = p->off_twr + align256(std::max<size_t>(p->twr.size(), 2) * 4);
+    p->off_twr = p->off_twc + align256(p->twc_max * 4);
+    p->bytes = p->off_twr + align256(p->twr_max * 4);
 }
 
 // Launch shape: C = columns per workgroup of the column stage (a power of
@@ -244,6 +264,37 @@ void choose_shape(lp_plan *p)
     p->t_rows = threads_for(p->m << logb);
 }
 
+void build_spec_tables(lp_plan *p)
+{
+    p->col_spec = lp::col_spec_index(static_cast<int>(p->py), p->col_variant);
+    p->twc.clear();
+    if (p->col_spec >= 0) {
+        const lp::ColSpec c = lp::kColSpecs[p->col_spec];
+        spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
+    }
+    p->row_spec = lp::row_spec_index(static_cast<int>(p->m), p->row_variant);
+    p->twr.clear();
+    if (p->row_spec >= 0) {
+        const lp::RowSpec c = lp::kRowSpecs[p->row_spec];
+        spec_tables(c.r0, c.r1, c.r2, &p->twr, p->twr_off);
+    }
+}
+
+int upload_spec_tables(lp_plan *p)
+{
+    hipError_t e;
+    if (!p->twc.empty() &&
+        (e = hipMemcpyAsync(p->ws + p->off_twc, p->twc.data(), p->twc.size() * 4, hipMemcpyHostToDevice,
+                            p->stream)) != hipSuccess)
+        return fail_hip(e, "twiddle upload");
+    if (!p->twr.empty() &&
+        (e = hipMemcpyAsync(p->ws + p->off_twr, p->twr.data(), p->twr.size() * 4, hipMemcpyHostToDevice,
+                            p->stream)) != hipSuccess)
+        return fail_hip(e, "twiddle upload");
+    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "twiddle upload");
+    return LP_OK;
+}
+
 int set_padding(lp_plan *p, int64_t py, int64_t px)
 {
     if (py < p->ny + p->ky - 1 || px < p->nx + p->kx - 1)
@@ -263,26 +314,18 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     p->h = p->m + 1;
     make_fft(p->m, &p->fx, &p->twx);
     make_fft(p->py, &p->fy, &p->twy);
-    p->col_spec = lp::col_spec_index(static_cast<int>(py));
-    p->twc.clear();
-    if (p->col_spec >= 0) {
-        const lp::ColSpec c = lp::kColSpecs[p->col_spec];
-        const int tabs[4][2] = {{c.r0, c.r1}, {c.r0 * c.r1, c.r2}, {c.r2, c.r1}, {c.r2 * c.r1, c.r0}};
-        for (int t = 0; t < 4; ++t) {
-            p->twc_off[t] = p->twc.size() / 2;
-            pass_table(tabs[t][0], tabs[t][1], &p->twc);
-        }
+    p->col_variant = 0;
+    p->row_variant = 0;
+    p->twc_max = p->twr_max = 2;
+    for (int k = 0; k < lp::col_spec_count(static_cast<int>(py)); ++k) {
+        const lp::ColSpec c = lp::kColSpecs[lp::col_spec_index(static_cast<int>(py), k)];
+        p->twc_max = std::max<size_t>(p->twc_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
     }
-    p->row_spec = lp::row_spec_index(static_cast<int>(p->m));
-    p->twr.clear();
-    if (p->row_spec >= 0) {
-        const lp::RowSpec c = lp::kRowSpecs[p->row_spec];
-        const int tabs[4][2] = {{c.r0, c.r1}, {c.r0 * c.r1, c.r2}, {c.r2, c.r1}, {c.r2 * c.r1, c.r0}};
-        for (int t = 0; t < 4; ++t) {
-            p->twr_off[t] = p->twr.size() / 2;
-            pass_table(tabs[t][0], tabs[t][1], &p->twr);
-        }
+    for (int k = 0; k < lp::row_spec_count(static_cast<int>(p->m)); ++k) {
+        const lp::RowSpec c = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(p->m), k)];
+        p->twr_max = std::max<size_t>(p->twr_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
     }
+    build_spec_tables(p);
     p->rtw.assign(2 * (p->m + 1), 0.f);
     for (int64_t k = 0; k <= p->m; ++k) {
         double c, s;
@@ -367,8 +410,8 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
         cr.tw_f2 = twc + p->twc_off[1];
         cr.tw_i1 = twc + p->twc_off[2];
         cr.tw_i2 = twc + p->twc_off[3];
-        if ((e = lp::launch_cols_reg(W, cr, static_cast<int>(p->py), static_cast<int>(p->h), p->form,
-                                     adjoint, p->stream)) != hipSuccess)
+        if ((e = lp::launch_cols_reg(W, cr, p->col_spec, static_cast<int>(p->h), p->form, adjoint,
+                                     p->stream)) != hipSuccess)
             return fail_hip(e, "column stage launch");
     } else if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream)) != hipSuccess) {
         return fail_hip(e, "column stage launch");
@@ -469,6 +512,57 @@ int lp_plan_kernels(const lp_plan *p)
     return (p->col_spec >= 0 || p->row_spec >= 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
 }
 
+int lp_plan_variant_count(const lp_plan *p, int stage)
+{
+    if (!p) return 0;
+    if (stage == LP_STAGE_ROWS) return lp::row_spec_count(static_cast<int>(p->m));
+    if (stage == LP_STAGE_COLUMNS) return lp::col_spec_count(static_cast<int>(p->py));
+    return 0;
+}
+
+int lp_plan_get_variant(const lp_plan *p, int stage)
+{
+    if (!p) return -1;
+    return stage == LP_STAGE_ROWS ? p->row_variant : stage == LP_STAGE_COLUMNS ? p->col_variant : -1;
+}
+
+int lp_plan_set_variant(lp_plan *p, int stage, int k)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (stage != LP_STAGE_ROWS && stage != LP_STAGE_COLUMNS)
+        return fail(LP_E_INVALID, "unknown stage %d", stage);
+    const int n = lp_plan_variant_count(p, stage);
+    if (k < 0 || k >= n) return fail(LP_E_INVALID, "variant %d out of range [0, %d)", k, n);
+    (stage == LP_STAGE_ROWS ? p->row_variant : p->col_variant) = k;
+    build_spec_tables(p);
+    return p->bound ? upload_spec_tables(p) : LP_OK;
+}
+
+int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
+{
+    clear_error();
+    if (!p || !info) return fail(LP_E_INVALID, "null argument");
+    int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (stage == LP_STAGE_ROWS) {
+        const int i = lp::row_spec_index(static_cast<int>(p->m), k);
+        if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
+        const lp::RowSpec c = lp::kRowSpecs[i];
+        const int t[8] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m};
+        std::copy(t, t + 8, v);
+    } else if (stage == LP_STAGE_COLUMNS) {
+        const int i = lp::col_spec_index(static_cast<int>(p->py), k);
+        if (i < 0) return fail(LP_E_INVALID, "no column variant %d", k);
+        const lp::ColSpec c = lp::kColSpecs[i];
+        const int t[8] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n};
+        std::copy(t, t + 8, v);
+    } else {
+        return fail(LP_E_INVALID, "unknown stage %d", stage);
+    }
+    for (int i = 0; i < n && i < 8; ++i) info[i] = v[i];
+    return LP_OK;
+}
+
 int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
 {
     clear_error();
@@ -498,13 +592,13 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
     p->bound = false;
     p->form = LP_FORM_NONE;
     struct { size_t off; const std::vector<float> *v; } up[] = {
-        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}, {p->off_twc, &p->twc},
-        {p->off_twr, &p->twr}};
+        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}};
     for (auto &u : up)
         if (!u.v->empty() && (e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
                                 p->stream)) != hipSuccess)
             return fail_hip(e, "twiddle upload");
-    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "twiddle upload");
+    const int rc = upload_spec_tables(p);
+    if (rc != LP_OK) return rc;
     p->bound = true;
     return LP_OK;
 }

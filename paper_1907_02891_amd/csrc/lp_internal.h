@@ -79,15 +79,22 @@ namespace lp {
 // Register-resident column stage: padded column length N = R0 * R1 * R2,
 // TF threads per column (one column per workgroup).
 // occ: minimum waves per SIMD asked of the register allocator (0: none).
+// Several entries may share a length: they are the variants a plan can pick
+// from (the first is the default; the autotuner measures the others).
 struct ColSpec {
     int n, tf, r0, r1, r2, occ;
 };
 constexpr ColSpec kColSpecs[] = {
     {5400, 360, 20, 18, 15, 5},
+    {5400, 360, 20, 15, 18, 4},
+    {5400, 360, 15, 18, 20, 5},
+    {5400, 225, 24, 25, 9, 0},
     {18432, 768, 32, 24, 24, 0},
     {2880, 240, 16, 12, 15, 0},
+    {2880, 240, 12, 16, 15, 0},
     {512, 64, 8, 8, 8, 0},
 };
+constexpr int kNumColSpecs = sizeof kColSpecs / sizeof kColSpecs[0];
 
 struct ColRegArgs {
     int32_t ny;          // stored rows per column
@@ -99,10 +106,10 @@ struct ColRegArgs {
     const float2 *tw_i2; // exp(-2 pi i j k / N),            k < R2 R1,   1 <= j < R0
 };
 
-// Index of the specialisation for column length n, or -1.
-int col_spec_index(int n);
-size_t col_spec_lds_bytes(int n);
-hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int form, bool conj_k,
+// Index of the k-th specialisation for column length n, or -1; number of them.
+int col_spec_index(int n, int k = 0);
+int col_spec_count(int n);
+hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
                            hipStream_t s);
 
 }  // namespace lp
@@ -111,16 +118,27 @@ namespace lp {
 
 // Register-resident row stages: half row length M = Px/2 = R0 * R1 * R2
 // (forward radix order; the inverse runs R2, R1, R0), TF threads per row,
-// B rows per workgroup.
+// B rows per workgroup; pf: row tiles per workgroup (1, or 2 with the second
+// tile's inputs prefetched into registers while the first is transformed; 0:
+// persistent, one workgroup per resident slot looping over tiles with the
+// next tile prefetched).
 struct RowSpec {
-    int m, tf, r0, r1, r2, b, occ;
+    int m, tf, r0, r1, r2, b, occ, pf;
 };
 constexpr RowSpec kRowSpecs[] = {
-    {2700, 128, 15, 15, 12, 2, 0},
-    {9216, 384, 16, 24, 24, 1, 0},
-    {1440, 128, 12, 12, 10, 2, 0},
-    {256, 64, 8, 8, 4, 4, 0},
+    {2700, 128, 15, 15, 12, 2, 4, 1},
+    {2700, 96, 12, 15, 15, 2, 3, 1},
+    {2700, 192, 15, 15, 12, 2, 3, 1},
+    {2700, 192, 15, 15, 12, 2, 3, 0},
+    {2700, 192, 15, 15, 12, 1, 3, 0},
+    {2700, 128, 15, 15, 12, 2, 3, 0},
+    {9216, 384, 16, 24, 24, 1, 2, 1},
+    {1440, 128, 12, 12, 10, 2, 5, 1},
+    {1440, 128, 12, 12, 10, 2, 3, 0},
+    {256, 64, 8, 8, 4, 4, 6, 1},
+    {256, 64, 8, 8, 4, 4, 4, 0},
 };
+constexpr int kNumRowSpecs = sizeof kRowSpecs / sizeof kRowSpecs[0];
 
 struct RowRegArgs {
     int32_t ny, nx;
@@ -128,8 +146,8 @@ struct RowRegArgs {
     const float2 *tw_f1, *tw_f2, *tw_i1, *tw_i2;  // as in ColRegArgs, for length M
 };
 
-int row_spec_index(int m);
-size_t row_spec_lds_bytes(int idx);
+int row_spec_index(int m, int k = 0);
+int row_spec_count(int m);
 int row_spec_rows(int idx);
 hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s);
 hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s);

@@ -432,75 +432,86 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 
     }
 }
 
-int col_spec_index(int n)
+int col_spec_index(int n, int k)
 {
-    for (int i = 0; i < static_cast<int>(sizeof kColSpecs / sizeof kColSpecs[0]); ++i)
-        if (kColSpecs[i].n == n) return i;
+    for (int i = 0; i < kNumColSpecs; ++i)
+        if (kColSpecs[i].n == n && k-- == 0) return i;
     return -1;
+}
+
+int col_spec_count(int n)
+{
+    int c = 0;
+    for (int i = 0; i < kNumColSpecs; ++i) c += kColSpecs[i].n == n;
+    return c;
 }
 
 static constexpr int xchg_words(int n, int r0, int r2)
 {
     const int a = lds_words(n, r0), c = lds_words(n, r2);
-    return (a > c ? a : c) > n ? (a > c ? a : c) : n;
-}
-
-size_t col_spec_lds_bytes(int n)
-{
-    const int i = col_spec_index(n);
-    return static_cast<size_t>(xchg_words(n, kColSpecs[i].r0, kColSpecs[i].r2)) * 8;
+    const int m = a > c ? a : c;
+    return m > n ? m : n;
 }
 
 template <int I>
-static hipError_t launch_col_spec(float2 *W, const ColRegArgs &a, int ncols, int form, bool conj_k,
-                                  hipStream_t s)
+static constexpr size_t col_lds_bytes()
+{
+    return static_cast<size_t>(xchg_words(kColSpecs[I].n, kColSpecs[I].r0, kColSpecs[I].r2)) * 8;
+}
+
+template <int I, int FORM, bool CONJ>
+static const void *col_fn()
 {
     constexpr ColSpec c = kColSpecs[I];
-    const dim3 g(ncols), t(((c.tf + 63) / 64) * 64);
-    const size_t lds = col_spec_lds_bytes(c.n);
-    if (form == 1)
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a);
-    else if (conj_k)
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a);
-    else
-        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a);
-    return hipGetLastError();
+    return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ>);
 }
 
 template <int I>
-static hipError_t set_col_spec_attr()
+static hipError_t col_attrs_from()
 {
-    constexpr ColSpec c = kColSpecs[I];
-    const void *fns[] = {
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>),
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>),
-        reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>),
-    };
-    for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if (e != hipSuccess) return e;
+    if constexpr (I >= kNumColSpecs) {
+        return hipSuccess;
+    } else {
+        const void *fns[] = {col_fn<I, 1, false>(), col_fn<I, 2, false>(), col_fn<I, 2, true>()};
+        for (const void *f : fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (e != hipSuccess) return e;
+        }
+        return col_attrs_from<I + 1>();
     }
-    return hipSuccess;
 }
 
-hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int n, int ncols, int form, bool conj_k,
+template <int I>
+static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int ncols, int form,
+                                  bool conj_k, hipStream_t s)
+{
+    if constexpr (I >= kNumColSpecs) {
+        return hipErrorInvalidValue;
+    } else {
+        if (idx != I) return launch_col_from<I + 1>(idx, W, a, ncols, form, conj_k, s);
+        constexpr ColSpec c = kColSpecs[I];
+        const dim3 g(ncols), t(((c.tf + 63) / 64) * 64);
+        const size_t lds = col_lds_bytes<I>();
+        if (form == 1)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a);
+        else if (conj_k)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a);
+        else
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a);
+        return hipGetLastError();
+    }
+}
+
+hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
                            hipStream_t s)
 {
     static bool attr = false;
     if (!attr) {
-        hipError_t e;
-        if ((e = set_col_spec_attr<0>()) != hipSuccess || (e = set_col_spec_attr<1>()) != hipSuccess ||
-            (e = set_col_spec_attr<2>()) != hipSuccess || (e = set_col_spec_attr<3>()) != hipSuccess)
-            return e;
+        hipError_t e = col_attrs_from<0>();
+        if (e != hipSuccess) return e;
         attr = true;
     }
-    switch (col_spec_index(n)) {
-        case 0: return launch_col_spec<0>(W, a, ncols, form, conj_k, s);
-        case 1: return launch_col_spec<1>(W, a, ncols, form, conj_k, s);
-        case 2: return launch_col_spec<2>(W, a, ncols, form, conj_k, s);
-        case 3: return launch_col_spec<3>(W, a, ncols, form, conj_k, s);
-        default: return hipErrorInvalidValue;
-    }
+    return launch_col_from<0>(idx, W, a, ncols, form, conj_k, s);
 }
 
 }  // namespace lp
@@ -543,7 +554,12 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // NB - tt, so that it holds both Z[k] and Z[M-k] for every k it produced and
 // the real-to-complex split happens in registers.  Column-major output:
 // X[k] of row r at W[k * ny + r].
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+// TPW tiles of B rows per workgroup, g and g + G (G = grid size); with two,
+// the second tile's inputs are loaded into registers before the first is
+// transformed, so its HBM reads overlap the arithmetic.  The code is straight
+// line (no loop) so that the DFT constants are not hoisted into registers
+// that stay live across iterations.
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__restrict__ Rm,
                                                              float2 *__restrict__ W, RowRegArgs a)
 {
@@ -552,82 +568,128 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     using F1 = RegPass<M, R1, R0, TF, B, R0>;
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
-    const int tid = threadIdx.x, b = tid % B, tt = tid / B;
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * B + b;
-    const bool rv = row < a.ny;
-    const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
+    static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
+    const int tid0 = threadIdx.x;
+    const int ntiles = (a.ny + B - 1) / B;
+    const int G = gridDim.x;
+    const int64_t ny = a.ny;
 
-    {
-        float2 x0[F0::S][R0];
+    auto load_tile = [&](float2 (&x)[F0::S][R0], int tile, int tt, int b) {
+        const int row = tile * B + b;
+        const bool rv = row < a.ny;
+        const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
 #pragma unroll
         for (int s = 0; s < F0::S; ++s) {
             const int i = tt + s * TF;
-            if (F0::NB % TF == 0 || i < F0::NB) {
+            if (F0::valid(i)) {
 #pragma unroll
-                for (int j = 0; j < R0; ++j) x0[s][j] = load_pair<EVEN_NX>(src, i + j * F0::NB, a.nx, rv);
+                for (int j = 0; j < R0; ++j) x[s][j] = load_pair<EVEN_NX>(src, i + j * F0::NB, a.nx, rv);
             }
         }
+    };
+
+    auto transform = [&](float2 (&x0)[F0::S][R0], int tile, int tt, int b) {
+        const int row = tile * B + b;
+        const bool rv = row < a.ny;
         F0::template butterfly<false>(x0, tt);
         F0::store(x0, lds, tt, b);
-    }
-    __syncthreads();
-    {
-        float2 x1[F1::S][R1];
-        F1::load(x1, lds, tt, b);
-        F1::template twiddle<false>(x1, a.tw_f1, tt);
-        F1::template butterfly<false>(x1, tt);
         __syncthreads();
-        F1::store(x1, lds, tt, b);
-    }
-    __syncthreads();
-    if (tt > NB / 2) return;
-    const int i1 = tt, i2 = NB - tt;
-    const bool two = (i2 != i1) && (i2 < NB);
-    float2 z1[R2], z2[R2];
-#pragma unroll
-    for (int j = 0; j < R2; ++j) z1[j] = lds[(i1 + j * NB) * B + b];
-    if (i1 > 0) {
-#pragma unroll
-        for (int j = 1; j < R2; ++j) z1[j] = cmul(z1[j], a.tw_f2[i1 * (R2 - 1) + j - 1]);
-    }
-    dftc<R2, false>(z1);
-    if (two) {
-#pragma unroll
-        for (int j = 0; j < R2; ++j) z2[j] = lds[(i2 + j * NB) * B + b];
-#pragma unroll
-        for (int j = 1; j < R2; ++j) z2[j] = cmul(z2[j], a.tw_f2[i2 * (R2 - 1) + j - 1]);
-        dftc<R2, false>(z2);
-    }
-    if (!rv) return;
-    float2 *dst = W + row;
-    const int64_t ny = a.ny;
-    if (i1 == 0) {
-#pragma unroll
-        for (int j = 0; j < R2; ++j) {
-            const int k = j * NB;
-            dst[k * ny] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+        {
+            float2 x1[F1::S][R1];
+            F1::load(x1, lds, tt, b);
+            F1::template twiddle<false>(x1, a.tw_f1, tt);
+            F1::template butterfly<false>(x1, tt);
+            __syncthreads();
+            F1::store(x1, lds, tt, b);
         }
-        dst[static_cast<int64_t>(M) * ny] = r2c_split(z1[0], z1[0], a.rtw[M]);
-    } else if (!two) {
+        __syncthreads();
+        if (tt <= NB / 2) {
+            const int i1 = tt, i2 = NB - tt;
+            const bool two = (i2 != i1) && (i2 < NB);
+            float2 z1[R2], z2[R2];
 #pragma unroll
-        for (int j = 0; j < R2; ++j) {
-            const int k = i1 + j * NB;
-            dst[k * ny] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+            for (int j = 0; j < R2; ++j) z1[j] = lds[(i1 + j * NB) * B + b];
+            if (i1 > 0) {
+#pragma unroll
+                for (int j = 1; j < R2; ++j) z1[j] = cmul(z1[j], a.tw_f2[i1 * (R2 - 1) + j - 1]);
+            }
+            dftc<R2, false>(z1);
+            if (two) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) z2[j] = lds[(i2 + j * NB) * B + b];
+#pragma unroll
+                for (int j = 1; j < R2; ++j) z2[j] = cmul(z2[j], a.tw_f2[i2 * (R2 - 1) + j - 1]);
+                dftc<R2, false>(z2);
+            }
+            if (rv) {
+                float2 *dst = W + row;
+                if (i1 == 0) {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k = j * NB;
+                        dst[k * ny] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+                    }
+                    dst[static_cast<int64_t>(M) * ny] = r2c_split(z1[0], z1[0], a.rtw[M]);
+                } else if (!two) {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k = i1 + j * NB;
+                        dst[k * ny] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k1 = i1 + j * NB, k2 = i2 + j * NB;
+                        dst[k1 * ny] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
+                        dst[k2 * ny] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                    }
+                }
+            }
+        }
+    };
+
+    const int t0 = xcd_tile(blockIdx.x, G);
+    if (t0 >= ntiles) return;
+    const int tt0 = tid0 / B, b0 = tid0 % B;
+    if constexpr (TPW == 1) {
+        float2 x0[F0::S][R0];
+        load_tile(x0, t0, tt0, b0);
+        transform(x0, t0, tt0, b0);
+    } else if constexpr (TPW == 2) {
+        const int t1 = t0 + G;
+        float2 x0[F0::S][R0], xn[F0::S][R0];
+        load_tile(x0, t0, tt0, b0);
+        if (t1 < ntiles) load_tile(xn, t1, tt0, b0);
+        transform(x0, t0, tt0, b0);
+        if (t1 < ntiles) {
+            __syncthreads();  // the second tile's first pass rewrites the exchange buffer
+            transform(xn, t1, tt0, b0);
         }
     } else {
+        // Persistent: tiles t0, t0 + G, ... with the next tile prefetched.  The
+        // thread index is re-read through opaque_v each iteration so that
+        // address arithmetic is not hoisted into loop-long registers.
+        float2 xn[F0::S][R0];
+        load_tile(xn, t0, tt0, b0);
+        for (int t = t0; t < ntiles; t += G) {
+            const int tid = opaque_v(tid0), tt = tid / B, b = tid % B;
+            float2 x0[F0::S][R0];
 #pragma unroll
-        for (int j = 0; j < R2; ++j) {
-            const int k1 = i1 + j * NB, k2 = i2 + j * NB;
-            dst[k1 * ny] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
-            dst[k2 * ny] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+            for (int s = 0; s < F0::S; ++s)
+#pragma unroll
+                for (int j = 0; j < R0; ++j) x0[s][j] = xn[s][j];
+            if (t + G < ntiles) load_tile(xn, t + G, tt, b);
+            transform(x0, t, tt, b);
+            __syncthreads();
         }
     }
 }
 
 // Inverse rows: the first pass (radix R2, NB = M/R2) pairs butterflies tt and
 // NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
-// and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+// and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).  TPW tiles
+// per workgroup as in the forward kernel.
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
                                                              float *__restrict__ Sm, RowRegArgs a)
 {
@@ -636,171 +698,250 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     using I2 = RegPass<M, R0, R2 * R1, TF, B, 0>;
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
-    const int tid = threadIdx.x, b = tid % B, tt = tid / B;
-    const int row = xcd_tile(blockIdx.x, gridDim.x) * B + b;
-    const bool rv = row < a.ny;
+    static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
+    const int tid0 = threadIdx.x;
+    const int ntiles = (a.ny + B - 1) / B;
+    const int G = gridDim.x;
     const int64_t ny = a.ny;
 
-    if (tt <= NB / 2) {
+    auto load_tile = [&](float2 (&xa)[R2], float2 (&xb)[R2], float2 &xm, int tile, int tt, int b) {
+        const bool pairer = tt <= NB / 2;
         const int i1 = tt, i2 = NB - tt;
-        const bool two = (i2 != i1) && (i2 < NB);
+        const bool two = pairer && (i2 != i1) && (i2 < NB);
+        const int row = tile * B + b;
+        const bool rv = row < a.ny;
         const float2 *src = W + (rv ? row : 0);
-        const float2 zero = make_float2(0.f, 0.f);
-        float2 xa[R2], xb[R2];
 #pragma unroll
         for (int j = 0; j < R2; ++j) {
-            xa[j] = rv ? src[static_cast<int64_t>(i1 + j * NB) * ny] : zero;
-            xb[j] = (rv && two) ? src[static_cast<int64_t>(i2 + j * NB) * ny] : zero;
+            xa[j] = make_float2(0.f, 0.f);
+            xb[j] = make_float2(0.f, 0.f);
         }
-        float2 za[R2], zb[R2];
-        if (i1 == 0) {
-            const float2 xm = rv ? src[static_cast<int64_t>(M) * ny] : zero;
+        xm = make_float2(0.f, 0.f);
+        if (rv && pairer) {
 #pragma unroll
-            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], j ? xa[R2 - j] : xm, a.rtw[j * NB]);
-        } else if (!two) {
+            for (int j = 0; j < R2; ++j) xa[j] = src[static_cast<int64_t>(i1 + j * NB) * ny];
+            if (two) {
 #pragma unroll
-            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], xa[R2 - 1 - j], a.rtw[i1 + j * NB]);
-        } else {
+                for (int j = 0; j < R2; ++j) xb[j] = src[static_cast<int64_t>(i2 + j * NB) * ny];
+            }
+            if (i1 == 0) xm = src[static_cast<int64_t>(M) * ny];
+        }
+    };
+
+    auto transform = [&](float2 (&xa)[R2], float2 (&xb)[R2], float2 xm, int tile, int tt, int b) {
+        const bool pairer = tt <= NB / 2;
+        const int i1 = tt, i2 = NB - tt;
+        const bool two = pairer && (i2 != i1) && (i2 < NB);
+        const int row = tile * B + b;
+        const bool rv = row < a.ny;
+        if (pairer) {
+            float2 za[R2], zb[R2];
+            if (i1 == 0) {
 #pragma unroll
-            for (int j = 0; j < R2; ++j) {
-                za[j] = c2r_merge(xa[j], xb[R2 - 1 - j], a.rtw[i1 + j * NB]);
-                zb[j] = c2r_merge(xb[j], xa[R2 - 1 - j], a.rtw[i2 + j * NB]);
+                for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], j ? xa[(R2 - j) % R2] : xm, a.rtw[j * NB]);
+            } else if (!two) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], xa[R2 - 1 - j], a.rtw[i1 + j * NB]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) {
+                    za[j] = c2r_merge(xa[j], xb[R2 - 1 - j], a.rtw[i1 + j * NB]);
+                    zb[j] = c2r_merge(xb[j], xa[R2 - 1 - j], a.rtw[i2 + j * NB]);
+                }
+            }
+            dftc<R2, true>(za);
+#pragma unroll
+            for (int j = 0; j < R2; ++j) lds[(i1 * lds_pitch(R2) + j) * B + b] = za[j];
+            if (two) {
+                dftc<R2, true>(zb);
+#pragma unroll
+                for (int j = 0; j < R2; ++j) lds[(i2 * lds_pitch(R2) + j) * B + b] = zb[j];
             }
         }
-        dftc<R2, true>(za);
-#pragma unroll
-        for (int j = 0; j < R2; ++j) lds[(i1 * lds_pitch(R2) + j) * B + b] = za[j];
-        if (two) {
-            dftc<R2, true>(zb);
-#pragma unroll
-            for (int j = 0; j < R2; ++j) lds[(i2 * lds_pitch(R2) + j) * B + b] = zb[j];
-        }
-    }
-    __syncthreads();
-    {
-        float2 y1[I1::S][R1];
-        I1::load(y1, lds, tt, b);
-        I1::template twiddle<true>(y1, a.tw_i1, tt);
-        I1::template butterfly<true>(y1, tt);
         __syncthreads();
-        I1::store(y1, lds, tt, b);
-    }
-    __syncthreads();
-    float2 y2[I2::S][R0];
-    I2::load(y2, lds, tt, b);
-    I2::template twiddle<true>(y2, a.tw_i2, tt);
-    I2::template butterfly<true>(y2, tt);
-    if (!rv) return;
-    float *dst = Sm + static_cast<int64_t>(row) * a.nx;
+        {
+            float2 y1[I1::S][R1];
+            I1::load(y1, lds, tt, b);
+            I1::template twiddle<true>(y1, a.tw_i1, tt);
+            I1::template butterfly<true>(y1, tt);
+            __syncthreads();
+            I1::store(y1, lds, tt, b);
+        }
+        __syncthreads();
+        float2 y2[I2::S][R0];
+        I2::load(y2, lds, tt, b);
+        I2::template twiddle<true>(y2, a.tw_i2, tt);
+        I2::template butterfly<true>(y2, tt);
+        if (rv) {
+            float *dst = Sm + static_cast<int64_t>(row) * a.nx;
 #pragma unroll
-    for (int s = 0; s < I2::S; ++s) {
-        const int i = tt + s * TF;
-        if (I2::NB % TF == 0 || i < I2::NB) {
+            for (int s = 0; s < I2::S; ++s) {
+                const int i = tt + s * TF;
+                if (I2::valid(i)) {
 #pragma unroll
-            for (int j = 0; j < R0; ++j) {
-                const int c0 = 2 * (i + j * I2::NB);
-                if (EVEN_NX) {
-                    if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
-                } else {
-                    if (c0 < a.nx) dst[c0] = y2[s][j].x;
-                    if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
+                    for (int j = 0; j < R0; ++j) {
+                        const int c0 = 2 * (i + j * I2::NB);
+                        if (EVEN_NX) {
+                            if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
+                        } else {
+                            if (c0 < a.nx) dst[c0] = y2[s][j].x;
+                            if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
+                        }
+                    }
                 }
             }
         }
+    };
+
+    const int t0 = xcd_tile(blockIdx.x, G);
+    if (t0 >= ntiles) return;
+    const int tt0 = tid0 / B, b0 = tid0 % B;
+    if constexpr (TPW == 1) {
+        float2 xa[R2], xb[R2], xm;
+        load_tile(xa, xb, xm, t0, tt0, b0);
+        transform(xa, xb, xm, t0, tt0, b0);
+    } else if constexpr (TPW == 2) {
+        const int t1 = t0 + G;
+        float2 xa[R2], xb[R2], xm, na[R2], nb2[R2], nm;
+        load_tile(xa, xb, xm, t0, tt0, b0);
+        if (t1 < ntiles) load_tile(na, nb2, nm, t1, tt0, b0);
+        transform(xa, xb, xm, t0, tt0, b0);
+        if (t1 < ntiles) {
+            __syncthreads();
+            transform(na, nb2, nm, t1, tt0, b0);
+        }
+    } else {
+        float2 na[R2], nb2[R2], nm;
+        load_tile(na, nb2, nm, t0, tt0, b0);
+        for (int t = t0; t < ntiles; t += G) {
+            const int tid = opaque_v(tid0), tt = tid / B, b = tid % B;
+            float2 xa[R2], xb[R2], xm = nm;
+#pragma unroll
+            for (int j = 0; j < R2; ++j) {
+                xa[j] = na[j];
+                xb[j] = nb2[j];
+            }
+            if (t + G < ntiles) load_tile(na, nb2, nm, t + G, tt, b);
+            transform(xa, xb, xm, t, tt, b);
+            __syncthreads();
+        }
     }
 }
 
-int row_spec_index(int m)
+int row_spec_index(int m, int k)
 {
-    for (int i = 0; i < static_cast<int>(sizeof kRowSpecs / sizeof kRowSpecs[0]); ++i)
-        if (kRowSpecs[i].m == m) return i;
+    for (int i = 0; i < kNumRowSpecs; ++i)
+        if (kRowSpecs[i].m == m && k-- == 0) return i;
     return -1;
 }
 
-size_t row_spec_lds_bytes(int idx)
+int row_spec_count(int m)
 {
-    const RowSpec &c = kRowSpecs[idx];
-    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * 8;
+    int c = 0;
+    for (int i = 0; i < kNumRowSpecs; ++i) c += kRowSpecs[i].m == m;
+    return c;
 }
 
 int row_spec_rows(int idx) { return kRowSpecs[idx].b; }
+
+template <int I>
+static constexpr size_t row_lds_bytes()
+{
+    constexpr RowSpec c = kRowSpecs[I];
+    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * 8;
+}
 
 template <int I, bool FWD, bool EVEN>
 static const void *row_fn()
 {
     constexpr RowSpec c = kRowSpecs[I];
     if constexpr (FWD)
-        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
     else
-        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
 }
 
 template <int I>
-static hipError_t set_row_spec_attr()
+static hipError_t row_attrs_from()
 {
-    const void *fns[] = {row_fn<I, true, true>(), row_fn<I, true, false>(), row_fn<I, false, true>(),
-                         row_fn<I, false, false>()};
-    for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
-        if (e != hipSuccess) return e;
+    if constexpr (I >= kNumRowSpecs) {
+        return hipSuccess;
+    } else {
+        const void *fns[] = {row_fn<I, true, true>(), row_fn<I, true, false>(), row_fn<I, false, true>(),
+                             row_fn<I, false, false>()};
+        for (const void *f : fns) {
+            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+            if (e != hipSuccess) return e;
+        }
+        return row_attrs_from<I + 1>();
     }
-    return hipSuccess;
 }
 
 static hipError_t row_attrs()
 {
     static bool attr = false;
     if (attr) return hipSuccess;
-    hipError_t e;
-    if ((e = set_row_spec_attr<0>()) != hipSuccess || (e = set_row_spec_attr<1>()) != hipSuccess ||
-        (e = set_row_spec_attr<2>()) != hipSuccess || (e = set_row_spec_attr<3>()) != hipSuccess)
-        return e;
-    attr = true;
-    return hipSuccess;
+    hipError_t e = row_attrs_from<0>();
+    if (e == hipSuccess) attr = true;
+    return e;
 }
 
 template <int I>
-static hipError_t launch_row_spec(const void *in, void *out, const RowRegArgs &a, bool fwd, hipStream_t s)
+static hipError_t launch_row_from(int idx, const void *in, void *out, const RowRegArgs &a, bool fwd,
+                                  hipStream_t s)
 {
-    constexpr RowSpec c = kRowSpecs[I];
-    const dim3 g((a.ny + c.b - 1) / c.b), t(c.tf * c.b);
-    const size_t lds = row_spec_lds_bytes(I);
-    const bool even = (a.nx % 2) == 0;
-    if (fwd) {
-        const float *R = static_cast<const float *>(in);
-        float2 *W = static_cast<float2 *>(out);
-        if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, R, W, a);
-        else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, R, W, a);
+    if constexpr (I >= kNumRowSpecs) {
+        return hipErrorInvalidValue;
     } else {
-        const float2 *W = static_cast<const float2 *>(in);
-        float *S = static_cast<float *>(out);
-        if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, W, S, a);
-        else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, W, S, a);
-    }
-    return hipGetLastError();
-}
-
-static hipError_t launch_row_any(const void *in, void *out, const RowRegArgs &a, int idx, bool fwd, hipStream_t s)
-{
-    hipError_t e = row_attrs();
-    if (e != hipSuccess) return e;
-    switch (idx) {
-        case 0: return launch_row_spec<0>(in, out, a, fwd, s);
-        case 1: return launch_row_spec<1>(in, out, a, fwd, s);
-        case 2: return launch_row_spec<2>(in, out, a, fwd, s);
-        case 3: return launch_row_spec<3>(in, out, a, fwd, s);
-        default: return hipErrorInvalidValue;
+        if (idx != I) return launch_row_from<I + 1>(idx, in, out, a, fwd, s);
+        constexpr RowSpec c = kRowSpecs[I];
+        constexpr int PF = c.pf;
+        const int ntiles = (a.ny + c.b - 1) / c.b;
+        int groups = PF ? (ntiles + PF - 1) / PF : ntiles;
+        if (PF == 0) {
+            static int resident[kNumRowSpecs][2] = {};
+            int &r = resident[I][fwd ? 0 : 1];
+            if (r == 0) {
+                int dev = 0, cus = 0, occ = 0;
+                const void *f = fwd ? row_fn<I, true, true>() : row_fn<I, false, true>();
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, f, c.tf * c.b, row_lds_bytes<I>()) != hipSuccess)
+                    return hipErrorInvalidValue;
+                r = cus * (occ > 0 ? occ : 1);
+            }
+            groups = ntiles < r ? ntiles : r;
+        }
+        const dim3 g(groups), t(c.tf * c.b);
+        const size_t lds = row_lds_bytes<I>();
+        const bool even = (a.nx % 2) == 0;
+        if (fwd) {
+            const float *R = static_cast<const float *>(in);
+            float2 *W = static_cast<float2 *>(out);
+            if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, R, W, a);
+            else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, R, W, a);
+        } else {
+            const float2 *W = static_cast<const float2 *>(in);
+            float *S = static_cast<float *>(out);
+            if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, W, S, a);
+            else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, W, S, a);
+        }
+        return hipGetLastError();
     }
 }
 
 hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s)
 {
-    return launch_row_any(R, W, a, idx, true, s);
+    hipError_t e = row_attrs();
+    if (e != hipSuccess) return e;
+    return launch_row_from<0>(idx, R, W, a, true, s);
 }
 
 hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s)
 {
-    return launch_row_any(W, S, a, idx, false, s);
+    hipError_t e = row_attrs();
+    if (e != hipSuccess) return e;
+    return launch_row_from<0>(idx, W, S, a, false, s);
 }
 
 }  // namespace lp

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LP_OK, LP_E_INVALID, LP_E_SIZE, LP_E_STATE, LP_E_NOMEM, LP_E_DEVICE = 0, -1, -2, -3, -4, -5
 FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
 KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
+STAGE_ROWS, STAGE_COLUMNS = 0, 1
 MAX_PY, MAX_PX = 20480, 40958
 
 _vp = ctypes.c_void_p
@@ -55,6 +56,10 @@ _SIGS = {
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
     "lp_plan_set_kernels": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_kernels": ([_vp], ctypes.c_int),
+    "lp_plan_variant_count": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_get_variant": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_set_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "lp_plan_variant_info": ([_vp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -205,6 +210,23 @@ class Plan:
     @property
     def kernels(self):
         return int(_lib.lp_plan_kernels(self._p))
+
+    def variant_count(self, stage):
+        return int(_lib.lp_plan_variant_count(self._p, int(stage)))
+
+    def variant(self, stage):
+        return int(_lib.lp_plan_get_variant(self._p, int(stage)))
+
+    def set_variant(self, stage, k):
+        _check(_lib.lp_plan_set_variant(self._p, int(stage), int(k)))
+
+    def variant_info(self, stage, k):
+        """dict(radices, threads per transform, transforms per workgroup,
+        min waves per SIMD, tiles per workgroup (0: persistent loop), length)."""
+        v = (ctypes.c_int * 8)()
+        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 8))
+        return {"radices": (v[0], v[1], v[2]), "threads": v[3], "per_group": v[4],
+                "min_waves": v[5], "tiles_per_group": v[6], "length": v[7]}
 
     def timing(self, enable=True):
         _check(_lib.lp_plan_timing(self._p, int(bool(enable))))

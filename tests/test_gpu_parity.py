@@ -251,3 +251,49 @@ def test_specialised_row_kernels(lp, torch, case):
     assert oracle.rel_l2(a, b) <= 2 * TOL
     g = spec.adjoint(x).cpu().numpy()
     assert_parity(g, oracle.adjoint_same(R, K), label=f"rows adjoint {case}")
+
+
+# ------------------------------------------------------ every tuned variant --
+
+VARIANT_CASES = [  # ny, nx, ky, kx, padding, symmetric
+    (37, 4093, 5, 401, (48, 5400), True), (4096, 9, 1201, 3, (5400, 12), False),
+    (11, 2049, 3, 801, (16, 2880), False), (2700, 7, 101, 3, (2880, 10), True),
+    (29, 255, 9, 3, (40, 512), False), (400, 15, 31, 1, (512, 16), True),
+]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES, ids=[f"p{c[4][0]}x{c[4][1]}" for c in VARIANT_CASES])
+def test_every_variant(lp, torch, case):
+    """Every compiled variant of every specialised stage, forward and adjoint."""
+    ny, nx, ky, kx, pad, sym = case
+    rng = np.random.default_rng(ny + 3 * nx)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    ref = oracle.conv_same(R, K)
+    refa = oracle.adjoint_same(R, K)
+    plan = lp.make_plan(K, ny, nx, padding=pad)
+    x = torch.from_numpy(R).cuda()
+    nvar = 0
+    for stage in (lp.STAGE_ROWS, lp.STAGE_COLUMNS):
+        for k in range(plan.variant_count(stage)):
+            plan.set_variant(stage, k)
+            info = plan.variant_info(stage, k)
+            assert_parity(plan.convolve(x).cpu().numpy(), ref, label=f"{case} stage {stage} v{k} {info}")
+            assert_parity(plan.adjoint(x).cpu().numpy(), refa, label=f"adj {case} stage {stage} v{k}")
+            nvar += 1
+        if plan.variant_count(stage):
+            plan.set_variant(stage, 0)
+    assert nvar >= 1
+
+
+def test_autotune_picks_a_variant(lp, torch, tmp_path, monkeypatch):
+    from paper_1907_02891_amd import tune
+    monkeypatch.setenv("LP_TUNE_CACHE", str(tmp_path / "tune.json"))
+    R, K = synth.small_inputs()
+    plan = lp.make_plan(K, *R.shape, padding=(512, 512))
+    x = torch.from_numpy(R).cuda()
+    rep = tune.autotune(plan, x, reps=3, warmup=1)
+    assert set(rep) == {"rows", "columns"}
+    assert_parity(plan.convolve(x).cpu().numpy(), oracle.conv_same(R, K), label="tuned small")
+    rep2 = tune.autotune(plan, x, reps=3, warmup=1)
+    assert rep2["rows"]["variant"] == rep["rows"]["variant"]

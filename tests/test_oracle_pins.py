@@ -325,3 +325,31 @@ def test_convolution_theorem_reproduces_same(shape, P):
     # conj(Khat) gives the transposed operator (the adjoint)
     Sa = (spectrum.dft_matrix(Py, +1) @ (np.conj(Kh) * Fr) @ spectrum.dft_matrix(Px, +1).T) / (Py * Px)
     np.testing.assert_allclose(Sa.real[:ny, :nx], oracle.adjoint_same(R, K), rtol=1e-11, atol=1e-12)
+
+
+def test_site_loss_gradient_by_central_differences():
+    """The gradient of L(R) = sum_i w_i (S(x_i) - m_i)^2 is the transposed
+    operator applied to 2 w (S - m) at the sites: checked against central
+    differences of the FP64 loss (exact for a quadratic loss up to round-off)."""
+    rng = np.random.default_rng(20)
+    ny, nx = 21, 17
+    R = rng.random((ny, nx))
+    K = rng.random((7, 5))
+    sites = rng.choice(ny * nx, 12, replace=False)
+    m = rng.random(12) + 0.5
+    w = 1.0 / m ** 2
+
+    def loss(Rx):
+        r = oracle.conv_same_pixels(Rx, K, sites) - m
+        return float(np.sum(w * r * r))
+
+    g = 2.0 * w * (oracle.conv_same_pixels(R, K, sites) - m)
+    grad = oracle.adjoint_sparse(sites, g, (ny, nx), K).ravel()
+    h = 0.5
+    for p in rng.choice(ny * nx, 30, replace=False):
+        Rp = R.copy().ravel()
+        Rp[p] += h
+        Lp = loss(Rp.reshape(ny, nx))
+        Rp[p] -= 2 * h
+        Lm = loss(Rp.reshape(ny, nx))
+        assert (Lp - Lm) / (2 * h) == pytest.approx(grad[p], rel=1e-9, abs=1e-11)

@@ -184,6 +184,51 @@ int lp_plan_variant_info(const lp_plan *plan, int stage, int k, int *info, int n
  * workgroup of the column stage, rows per workgroup of the row stages. */
 int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);
 
+/* ---------------------------------------------------------------- batch --
+ * Many independent maps (tiles, spectral bands) convolved with a few kernels:
+ * the factorable-classes case of Sec. 2.2 (Eq. 4), handled map by map.  Map t
+ * has ny[t] x nx[t] pixels and uses kernel psf_id[t] (0 <= psf_id < n_psf,
+ * kernel p of ky[p] x kx[p]).  Each map gets the smallest padded size on each
+ * axis, >= n + k - 1, for which the library has specialised kernels; maps
+ * sharing a padded size form a class, and maps of a class sharing a kernel
+ * share one stored spectrum.  All host arrays are read during the call only.
+ * Returns NULL on error: LP_E_INVALID (bad sizes, ids, pitch), LP_E_SIZE (no
+ * specialised padded size is large enough). */
+lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx,
+                          const int *psf_id, int n_psf, const int64_t *ky,
+                          const int64_t *kx, double pitch_km);
+void lp_batch_destroy(lp_batch *batch);
+size_t lp_batch_workspace_bytes(const lp_batch *batch);
+
+/* Caller-owned device workspace (>= lp_batch_workspace_bytes, 256-byte
+ * aligned) and stream; uploads the twiddle tables and synchronises. */
+int lp_batch_bind(lp_batch *batch, void *dev_ws, size_t bytes, void *stream);
+
+/* psfs[p]: host FP64 ky[p]*kx[p] row-major kernels (Eq. 10 spectra per class,
+ * as lp_kernel_spectrum).  Synchronises. */
+int lp_batch_kernel_spectra(lp_batch *batch, const double *const *psfs);
+
+/* radiance[t], out[t]: device FP32 ny[t]*nx[t] per map (host array of device
+ * pointers; out[t] may alias radiance[t]).  Per class and spectrum form, one
+ * launch per stage covers every map; the whole sequence is captured once
+ * into a HIP graph and replayed on the bound stream.  When the pointer set
+ * differs from the previous call the per-map device table is re-uploaded
+ * (synchronising the stream); the graph reads it and is kept. */
+int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *const *out);
+
+/* Graph replay (default) or direct launches (enable = 0). */
+int lp_batch_use_graph(lp_batch *batch, int enable);
+
+/* Classes: count; info for class g: {Py, Px, maps, row variants, column
+ * variants, largest map row count} (up to n values); the class of map t. */
+int lp_batch_group_count(const lp_batch *batch);
+int lp_batch_group_info(const lp_batch *batch, int g, int64_t *info, int n);
+int lp_batch_tile_group(const lp_batch *batch, int t);
+
+/* Per-class kernel variants (as lp_plan_set_variant); invalidates the graph. */
+int lp_batch_set_variant(lp_batch *batch, int g, int stage, int k);
+int lp_batch_get_variant(const lp_batch *batch, int g, int stage);
+
 #ifdef __cplusplus
 }
 #endif

@@ -752,3 +752,472 @@ int lp_plan_stage_ms(lp_plan *p, double *ms, int n, int *calls)
 }
 
 }  // extern "C"
+
+// ====================================================================== batch
+// Many maps (tiles x bands) with a few kernels (Eq. 4 applied tile by tile).
+// Every map goes to a padding class (Py, Px): the smallest lengths >= n+k-1
+// on each axis that have specialised kernels.  Per class and spectrum form,
+// one launch per stage covers all its maps (grid.y = map), reading per-map
+// pointers from a device table; spectra are shared per (class, kernel).  The
+// whole launch sequence is captured once into a HIP graph and replayed.
+struct lp_batch {
+    struct Group {
+        int64_t py = 0, px = 0, m = 0, h = 0;
+        int col_variant = 0, row_variant = 0, col_spec = -1, row_spec = -1;
+        std::vector<float> twc, twr, rtw;
+        size_t twc_off[4] = {0, 0, 0, 0}, twr_off[4] = {0, 0, 0, 0};
+        size_t twc_max = 2, twr_max = 2;
+        size_t off_twc = 0, off_twr = 0, off_rtw = 0;
+        std::vector<int> items;
+        std::vector<int> psfs;       // distinct kernel ids used in this class
+        std::vector<size_t> off_kh;  // per psfs[j]
+        std::vector<int> form;       // per psfs[j]
+        int64_t max_ny = 0;
+        bool odd_nx = false;
+        size_t off_tab[2] = {0, 0};  // BatchItem arrays: quadrant-form maps, complex-form maps
+        std::vector<lp::BatchItem> tab[2];
+    };
+    int n = 0, n_psf = 0;
+    std::vector<int64_t> ny, nx, ky, kx;
+    std::vector<int> psf;
+    double pitch = 0;
+    std::vector<Group> groups;
+    std::vector<int> item_group;
+    std::vector<size_t> off_w;
+    size_t off_scratch = 0, bytes = 0;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false, spectra = false;
+    bool use_graph = true, graph_ok = false, tables_dirty = true;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const float *> last_in;
+    std::vector<float *> last_out;
+};
+
+namespace {
+
+std::vector<int64_t> spec_lengths(bool columns)
+{
+    std::vector<int64_t> v;
+    if (columns) {
+        for (int i = 0; i < lp::kNumColSpecs; ++i) v.push_back(lp::kColSpecs[i].n);
+    } else {
+        for (int i = 0; i < lp::kNumRowSpecs; ++i) v.push_back(2 * static_cast<int64_t>(lp::kRowSpecs[i].m));
+    }
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    return v;
+}
+
+void batch_group_tables(lp_batch::Group &g)
+{
+    g.col_spec = lp::col_spec_index(static_cast<int>(g.py), g.col_variant);
+    g.row_spec = lp::row_spec_index(static_cast<int>(g.m), g.row_variant);
+    const lp::ColSpec c = lp::kColSpecs[g.col_spec];
+    const lp::RowSpec r = lp::kRowSpecs[g.row_spec];
+    spec_tables(c.r0, c.r1, c.r2, &g.twc, g.twc_off);
+    spec_tables(r.r0, r.r1, r.r2, &g.twr, g.twr_off);
+}
+
+void batch_destroy_graph(lp_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_ok = false;
+}
+
+int batch_upload_group_tables(lp_batch *b, lp_batch::Group &g)
+{
+    hipError_t e;
+    if ((e = hipMemcpyAsync(b->ws + g.off_twc, g.twc.data(), g.twc.size() * 4, hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->ws + g.off_twr, g.twr.data(), g.twr.size() * 4, hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->ws + g.off_rtw, g.rtw.data(), g.rtw.size() * 4, hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+        return fail_hip(e, "batch table upload");
+    return LP_OK;
+}
+
+// Enqueue every launch of one batched call on stream s.
+hipError_t batch_launch_all(lp_batch *b, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (auto &g : b->groups) {
+        const float2 *twr = reinterpret_cast<const float2 *>(b->ws + g.off_twr);
+        const float2 *twc = reinterpret_cast<const float2 *>(b->ws + g.off_twc);
+        lp::RowRegArgs rr{};
+        rr.ny = static_cast<int32_t>(g.max_ny);
+        rr.nx = g.odd_nx ? 1 : 2;
+        rr.rtw = reinterpret_cast<const float2 *>(b->ws + g.off_rtw);
+        rr.tw_f1 = twr + g.twr_off[0];
+        rr.tw_f2 = twr + g.twr_off[1];
+        rr.tw_i1 = twr + g.twr_off[2];
+        rr.tw_i2 = twr + g.twr_off[3];
+        lp::ColRegArgs cr{};
+        cr.ny = 0;
+        cr.tw_f1 = twc + g.twc_off[0];
+        cr.tw_f2 = twc + g.twc_off[1];
+        cr.tw_i1 = twc + g.twc_off[2];
+        cr.tw_i2 = twc + g.twc_off[3];
+        for (int f = 0; f < 2; ++f) {
+            const int nit = static_cast<int>(g.tab[f].size());
+            if (nit == 0) continue;
+            const lp::BatchItem *items = reinterpret_cast<const lp::BatchItem *>(b->ws + g.off_tab[f]);
+            cr.ku = static_cast<int32_t>(f == 0 ? g.py / 2 + 1 : g.py);
+            if ((e = lp::launch_rows_r2c_reg(nullptr, nullptr, rr, g.row_spec, s, items, nit)) != hipSuccess ||
+                (e = lp::launch_cols_reg(nullptr, cr, g.col_spec, static_cast<int>(g.h), f == 0 ? 1 : 2, false,
+                                         s, items, nit)) != hipSuccess ||
+                (e = lp::launch_rows_c2r_reg(nullptr, nullptr, rr, g.row_spec, s, items, nit)) != hipSuccess)
+                return e;
+        }
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
+                          const int64_t *ky, const int64_t *kx, double pitch_km)
+{
+    clear_error();
+    if (n_tiles <= 0 || n_psf <= 0 || !ny || !nx || !psf_id || !ky || !kx) {
+        fail(LP_E_INVALID, "batch: empty or null arguments");
+        return nullptr;
+    }
+    if (!(pitch_km > 0.0) || !std::isfinite(pitch_km)) {
+        fail(LP_E_INVALID, "pitch must be positive and finite");
+        return nullptr;
+    }
+    for (int p = 0; p < n_psf; ++p)
+        if (ky[p] <= 0 || kx[p] <= 0) {
+            fail(LP_E_INVALID, "kernel %d has a non-positive size", p);
+            return nullptr;
+        }
+    const std::vector<int64_t> ly = spec_lengths(true), lx = spec_lengths(false);
+    lp_batch *b = new (std::nothrow) lp_batch();
+    if (!b) {
+        fail(LP_E_NOMEM, "out of host memory");
+        return nullptr;
+    }
+    b->n = n_tiles;
+    b->n_psf = n_psf;
+    b->pitch = pitch_km;
+    b->ny.assign(ny, ny + n_tiles);
+    b->nx.assign(nx, nx + n_tiles);
+    b->psf.assign(psf_id, psf_id + n_tiles);
+    b->ky.assign(ky, ky + n_psf);
+    b->kx.assign(kx, kx + n_psf);
+    b->item_group.assign(n_tiles, -1);
+    for (int t = 0; t < n_tiles; ++t) {
+        if (ny[t] <= 0 || nx[t] <= 0 || psf_id[t] < 0 || psf_id[t] >= n_psf) {
+            fail(LP_E_INVALID, "tile %d: bad size or kernel id", t);
+            delete b;
+            return nullptr;
+        }
+        const int64_t need_y = ny[t] + ky[psf_id[t]] - 1, need_x = nx[t] + kx[psf_id[t]] - 1;
+        auto py = std::lower_bound(ly.begin(), ly.end(), need_y);
+        auto px = std::lower_bound(lx.begin(), lx.end(), need_x);
+        if (py == ly.end() || px == lx.end()) {
+            fail(LP_E_SIZE, "tile %d (%lld x %lld, kernel %d) needs padding beyond the specialised sizes",
+                 t, (long long)ny[t], (long long)nx[t], psf_id[t]);
+            delete b;
+            return nullptr;
+        }
+        int gi = -1;
+        for (size_t k = 0; k < b->groups.size(); ++k)
+            if (b->groups[k].py == *py && b->groups[k].px == *px) gi = static_cast<int>(k);
+        if (gi < 0) {
+            lp_batch::Group g;
+            g.py = *py;
+            g.px = *px;
+            g.m = g.px / 2;
+            g.h = g.m + 1;
+            for (int k = 0; k < lp::col_spec_count(static_cast<int>(g.py)); ++k) {
+                const lp::ColSpec c = lp::kColSpecs[lp::col_spec_index(static_cast<int>(g.py), k)];
+                g.twc_max = std::max<size_t>(g.twc_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
+            }
+            for (int k = 0; k < lp::row_spec_count(static_cast<int>(g.m)); ++k) {
+                const lp::RowSpec c = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(g.m), k)];
+                g.twr_max = std::max<size_t>(g.twr_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
+            }
+            batch_group_tables(g);
+            g.rtw.assign(2 * (g.m + 1), 0.f);
+            for (int64_t k = 0; k <= g.m; ++k) {
+                double c, s;
+                exp_frac(k, g.px, &c, &s);
+                g.rtw[2 * k] = static_cast<float>(c);
+                g.rtw[2 * k + 1] = static_cast<float>(-s);
+            }
+            b->groups.push_back(std::move(g));
+            gi = static_cast<int>(b->groups.size()) - 1;
+        }
+        lp_batch::Group &g = b->groups[gi];
+        g.items.push_back(t);
+        g.max_ny = std::max(g.max_ny, ny[t]);
+        g.odd_nx = g.odd_nx || (nx[t] % 2 != 0);
+        if (std::find(g.psfs.begin(), g.psfs.end(), psf_id[t]) == g.psfs.end()) g.psfs.push_back(psf_id[t]);
+        b->item_group[t] = gi;
+    }
+    // workspace layout
+    size_t off = 0, wtotal = 0;
+    b->off_w.assign(n_tiles, 0);
+    for (int t = 0; t < n_tiles; ++t) {
+        const lp_batch::Group &g = b->groups[b->item_group[t]];
+        b->off_w[t] = off;
+        off += align256(static_cast<size_t>(g.h) * ny[t] * 8);
+    }
+    wtotal = off;
+    size_t scratch = 0;
+    for (auto &g : b->groups)
+        for (int p : g.psfs)
+            scratch = std::max(scratch, align256(ky[p] * kx[p] * 8) + align256(ky[p] * g.h * 16) +
+                                            align256(g.px * 16) + align256(g.py * 16));
+    b->off_scratch = 0;  // overlaps the intermediates (idle while spectra are made)
+    off = align256(std::max(wtotal, scratch));
+    for (auto &g : b->groups) {
+        g.off_kh.clear();
+        g.form.assign(g.psfs.size(), LP_FORM_NONE);
+        for (size_t j = 0; j < g.psfs.size(); ++j) {
+            g.off_kh.push_back(off);
+            off += align256(static_cast<size_t>(g.py) * g.h * 8);
+        }
+        g.off_twc = off;
+        off += align256(g.twc_max * 4);
+        g.off_twr = off;
+        off += align256(g.twr_max * 4);
+        g.off_rtw = off;
+        off += align256(g.rtw.size() * 4);
+        for (int f = 0; f < 2; ++f) {
+            g.off_tab[f] = off;
+            off += align256(g.items.size() * sizeof(lp::BatchItem));
+        }
+    }
+    b->bytes = off;
+    return b;
+}
+
+void lp_batch_destroy(lp_batch *b)
+{
+    if (!b) return;
+    batch_destroy_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+size_t lp_batch_workspace_bytes(const lp_batch *b) { return b ? b->bytes : 0; }
+
+int lp_batch_bind(lp_batch *b, void *ws, size_t bytes, void *stream)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (!ws) return fail(LP_E_INVALID, "null workspace");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(LP_E_INVALID, "workspace not 256-byte aligned");
+    if (bytes < b->bytes)
+        return fail(LP_E_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, b->bytes);
+    hipError_t e;
+    if ((e = lp::set_spec_attributes()) != hipSuccess) return fail_hip(e, "kernel attributes");
+    batch_destroy_graph(b);
+    b->ws = static_cast<char *>(ws);
+    b->stream = static_cast<hipStream_t>(stream);
+    b->bound = false;
+    b->spectra = false;
+    b->tables_dirty = true;
+    for (auto &g : b->groups) {
+        const int rc = batch_upload_group_tables(b, g);
+        if (rc != LP_OK) return rc;
+    }
+    b->bound = true;
+    return LP_OK;
+}
+
+int lp_batch_kernel_spectra(lp_batch *b, const double *const *psfs)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (!psfs) return fail(LP_E_INVALID, "null kernel array");
+    for (int p = 0; p < b->n_psf; ++p) {
+        if (!psfs[p]) return fail(LP_E_INVALID, "kernel %d is null", p);
+        for (int64_t i = 0; i < b->ky[p] * b->kx[p]; ++i)
+            if (!std::isfinite(psfs[p][i])) return fail(LP_E_INVALID, "kernel %d entry %lld is not finite", p, (long long)i);
+    }
+    if (!b->bound) return fail(LP_E_STATE, "lp_batch_kernel_spectra before lp_batch_bind");
+    hipError_t e;
+    for (auto &g : b->groups) {
+        std::vector<double> tabx(2 * g.px), taby(2 * g.py);
+        for (int64_t m = 0; m < g.px; ++m) {
+            double c, s;
+            exp_frac(m, g.px, &c, &s);
+            tabx[2 * m] = c;
+            tabx[2 * m + 1] = -s;
+        }
+        for (int64_t m = 0; m < g.py; ++m) {
+            double c, s;
+            exp_frac(m, g.py, &c, &s);
+            taby[2 * m] = c;
+            taby[2 * m + 1] = -s;
+        }
+        for (size_t j = 0; j < g.psfs.size(); ++j) {
+            const int p = g.psfs[j];
+            const int64_t ky = b->ky[p], kx = b->kx[p];
+            const double *K = psfs[p];
+            bool sym = (ky % 2 == 1) && (kx % 2 == 1);
+            for (int64_t a = 0; sym && a < ky; ++a)
+                for (int64_t c = 0; c < kx; ++c) {
+                    const double v = K[a * kx + c];
+                    if (v != K[(ky - 1 - a) * kx + c] || v != K[a * kx + (kx - 1 - c)]) { sym = false; break; }
+                }
+            char *sc = b->ws + b->off_scratch;
+            double *dK = reinterpret_cast<double *>(sc);
+            double2 *dT1 = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8));
+            double2 *dTabx = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8) + align256(ky * g.h * 16));
+            double2 *dTaby = reinterpret_cast<double2 *>(reinterpret_cast<char *>(dTabx) + align256(g.px * 16));
+            if ((e = hipMemcpyAsync(dK, K, ky * kx * 8, hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(dTabx, tabx.data(), tabx.size() * 8, hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+                (e = hipMemcpyAsync(dTaby, taby.data(), taby.size() * 8, hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+                return fail_hip(e, "kernel upload");
+            if ((e = lp::launch_spec_rows(dK, static_cast<int>(ky), static_cast<int>(kx), static_cast<int>((kx - 1) / 2),
+                                          static_cast<int>(g.px), static_cast<int>(g.h), dTabx, dT1, b->stream)) != hipSuccess)
+                return fail_hip(e, "spectrum rows launch");
+            const int ku = static_cast<int>(sym ? g.py / 2 + 1 : g.py);
+            const double scale = 1.0 / (static_cast<double>(g.py) * static_cast<double>(g.px));
+            const int form = sym ? LP_FORM_REAL_QUADRANT : LP_FORM_COMPLEX;
+            if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), static_cast<int>((ky - 1) / 2), static_cast<int>(g.py),
+                                          ku, static_cast<int>(g.h), 0, static_cast<int>(g.h), dTaby, scale, form,
+                                          b->ws + g.off_kh[j], b->stream)) != hipSuccess)
+                return fail_hip(e, "spectrum columns launch");
+            // the scratch is reused by the next kernel: wait for this one
+            if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return fail_hip(e, "kernel spectrum");
+            g.form[j] = form;
+        }
+    }
+    b->spectra = true;
+    b->tables_dirty = true;
+    batch_destroy_graph(b);
+    return LP_OK;
+}
+
+int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const *out)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (!radiance || !out) return fail(LP_E_INVALID, "null pointer arrays");
+    for (int t = 0; t < b->n; ++t)
+        if (!radiance[t] || !out[t]) return fail(LP_E_INVALID, "tile %d: null data pointer", t);
+    if (!b->bound) return fail(LP_E_NOMEM, "no workspace bound");
+    if (!b->spectra) return fail(LP_E_STATE, "kernel spectra not computed");
+    hipError_t e;
+    bool changed = b->tables_dirty || b->last_in.size() != static_cast<size_t>(b->n);
+    for (int t = 0; !changed && t < b->n; ++t) changed = b->last_in[t] != radiance[t] || b->last_out[t] != out[t];
+    if (changed) {
+        for (auto &g : b->groups) {
+            g.tab[0].clear();
+            g.tab[1].clear();
+            for (int t : g.items) {
+                const size_t j = std::find(g.psfs.begin(), g.psfs.end(), b->psf[t]) - g.psfs.begin();
+                lp::BatchItem it{};
+                it.in = radiance[t];
+                it.out = out[t];
+                it.w = reinterpret_cast<float2 *>(b->ws + b->off_w[t]);
+                it.kh = b->ws + g.off_kh[j];
+                it.ny = static_cast<int32_t>(b->ny[t]);
+                it.nx = static_cast<int32_t>(b->nx[t]);
+                g.tab[g.form[j] == LP_FORM_REAL_QUADRANT ? 0 : 1].push_back(it);
+            }
+            for (int f = 0; f < 2; ++f)
+                if (!g.tab[f].empty() &&
+                    (e = hipMemcpyAsync(b->ws + g.off_tab[f], g.tab[f].data(), g.tab[f].size() * sizeof(lp::BatchItem),
+                                        hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+                    return fail_hip(e, "batch table upload");
+        }
+        if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return fail_hip(e, "batch table upload");
+        // the launch grids depend on the per-form split: rebuild the graph
+        if (b->tables_dirty) batch_destroy_graph(b);
+        b->last_in.assign(radiance, radiance + b->n);
+        b->last_out.assign(out, out + b->n);
+        b->tables_dirty = false;
+    }
+    if (!b->use_graph) {
+        if ((e = batch_launch_all(b, b->stream)) != hipSuccess) return fail_hip(e, "batched launch");
+        return LP_OK;
+    }
+    if (!b->graph_ok) {
+        if (!b->cap && (e = hipStreamCreate(&b->cap)) != hipSuccess) return fail_hip(e, "capture stream");
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return fail_hip(e, "graph capture");
+        const hipError_t le = batch_launch_all(b, b->cap);
+        hipGraph_t gph = nullptr;
+        e = hipStreamEndCapture(b->cap, &gph);
+        if (le != hipSuccess) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return fail_hip(le, "batched launch (capture)");
+        }
+        if (e != hipSuccess) return fail_hip(e, "graph capture");
+        b->graph = gph;
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            batch_destroy_graph(b);
+            return fail_hip(e, "graph instantiate");
+        }
+        b->graph_ok = true;
+    }
+    if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return fail_hip(e, "graph launch");
+    return LP_OK;
+}
+
+int lp_batch_use_graph(lp_batch *b, int enable)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    b->use_graph = enable != 0;
+    return LP_OK;
+}
+
+int lp_batch_group_count(const lp_batch *b) { return b ? static_cast<int>(b->groups.size()) : 0; }
+
+int lp_batch_group_info(const lp_batch *b, int g, int64_t *info, int n)
+{
+    clear_error();
+    if (!b || !info) return fail(LP_E_INVALID, "null argument");
+    if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
+    const lp_batch::Group &gr = b->groups[g];
+    const int64_t v[6] = {gr.py, gr.px, static_cast<int64_t>(gr.items.size()),
+                          lp::row_spec_count(static_cast<int>(gr.m)), lp::col_spec_count(static_cast<int>(gr.py)),
+                          gr.max_ny};
+    for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
+    return LP_OK;
+}
+
+int lp_batch_tile_group(const lp_batch *b, int t) { return (b && t >= 0 && t < b->n) ? b->item_group[t] : -1; }
+
+int lp_batch_set_variant(lp_batch *b, int g, int stage, int k)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
+    lp_batch::Group &gr = b->groups[g];
+    if (stage == LP_STAGE_ROWS) {
+        if (k < 0 || k >= lp::row_spec_count(static_cast<int>(gr.m))) return fail(LP_E_INVALID, "no row variant %d", k);
+        gr.row_variant = k;
+    } else if (stage == LP_STAGE_COLUMNS) {
+        if (k < 0 || k >= lp::col_spec_count(static_cast<int>(gr.py))) return fail(LP_E_INVALID, "no column variant %d", k);
+        gr.col_variant = k;
+    } else {
+        return fail(LP_E_INVALID, "unknown stage %d", stage);
+    }
+    batch_group_tables(gr);
+    batch_destroy_graph(b);
+    return b->bound ? batch_upload_group_tables(b, gr) : LP_OK;
+}
+
+int lp_batch_get_variant(const lp_batch *b, int g, int stage)
+{
+    if (!b || g < 0 || g >= static_cast<int>(b->groups.size())) return -1;
+    return stage == LP_STAGE_ROWS ? b->groups[g].row_variant
+                                  : stage == LP_STAGE_COLUMNS ? b->groups[g].col_variant : -1;
+}
+
+}  // extern "C"

@@ -93,6 +93,13 @@ constexpr ColSpec kColSpecs[] = {
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},
     {512, 64, 8, 8, 8, 0},
+    {1800, 180, 12, 10, 15, 0},
+    {2048, 256, 16, 16, 8, 0},
+    {2160, 180, 12, 12, 15, 0},
+    {2592, 216, 12, 12, 18, 0},
+    {3240, 270, 18, 12, 15, 0},
+    {3600, 240, 16, 15, 15, 0},
+    {4320, 360, 20, 18, 12, 5},
 };
 constexpr int kNumColSpecs = sizeof kColSpecs / sizeof kColSpecs[0];
 
@@ -106,11 +113,22 @@ struct ColRegArgs {
     const float2 *tw_i2; // exp(-2 pi i j k / N),            k < R2 R1,   1 <= j < R0
 };
 
+// One map of a batched launch: the specialised kernels take a device array of
+// these and read item blockIdx.y (all items of a launch share the padded
+// size, the spectrum form and the twiddle tables).
+struct BatchItem {
+    const float *in;   // radiance, ny x nx
+    float *out;        // output map, ny x nx
+    float2 *w;         // intermediate, column-major, (Px/2+1) columns of ny
+    const void *kh;    // spectrum of the item's kernel at this padded size
+    int32_t ny, nx;
+};
+
 // Index of the k-th specialisation for column length n, or -1; number of them.
 int col_spec_index(int n, int k = 0);
 int col_spec_count(int n);
 hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
-                           hipStream_t s);
+                           hipStream_t s, const BatchItem *items = nullptr, int nitems = 1);
 
 }  // namespace lp
 
@@ -137,6 +155,13 @@ constexpr RowSpec kRowSpecs[] = {
     {1440, 128, 12, 12, 10, 2, 3, 0},
     {256, 64, 8, 8, 4, 4, 6, 1},
     {256, 64, 8, 8, 4, 4, 4, 0},
+    {900, 100, 10, 9, 10, 2, 0, 1},
+    {1024, 128, 8, 8, 16, 2, 0, 1},
+    {1080, 120, 9, 10, 12, 2, 0, 1},
+    {1296, 108, 12, 12, 9, 2, 0, 1},
+    {1620, 180, 12, 9, 15, 2, 0, 1},
+    {1800, 180, 12, 10, 15, 2, 0, 1},
+    {2160, 180, 12, 12, 15, 2, 0, 1},
 };
 constexpr int kNumRowSpecs = sizeof kRowSpecs / sizeof kRowSpecs[0];
 
@@ -149,7 +174,12 @@ struct RowRegArgs {
 int row_spec_index(int m, int k = 0);
 int row_spec_count(int m);
 int row_spec_rows(int idx);
-hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s);
-hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s);
+// Batched (items != nullptr): a.ny is the largest item row count, a.nx odd if
+// any item's width is odd.
+hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s,
+                               const BatchItem *items = nullptr, int nitems = 1);
+hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s,
+                               const BatchItem *items = nullptr, int nitems = 1);
+hipError_t set_spec_attributes();
 
 }  // namespace lp

@@ -331,7 +331,8 @@ namespace lp {
 // only rows < ny read or written.  Column-major intermediate: column v is the
 // contiguous run W[v * ny .. v * ny + ny).
 template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ>
-__global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a)
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a,
+                                                                         const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
     using F0 = RegPass<N, R0, 1, TF, 1, 0>;
@@ -343,7 +344,13 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 
     const int tt = threadIdx.x;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
-    const int ny = a.ny;
+    int ny = a.ny;
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        W = it.w;
+        ny = it.ny;
+        a.kh = it.kh;
+    }
     float2 *col = W + static_cast<int64_t>(v) * ny;
 
     float2 x0[F0::S][R0];
@@ -483,35 +490,31 @@ static hipError_t col_attrs_from()
 
 template <int I>
 static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int ncols, int form,
-                                  bool conj_k, hipStream_t s)
+                                  bool conj_k, hipStream_t s, const BatchItem *items, int nitems)
 {
     if constexpr (I >= kNumColSpecs) {
         return hipErrorInvalidValue;
     } else {
-        if (idx != I) return launch_col_from<I + 1>(idx, W, a, ncols, form, conj_k, s);
+        if (idx != I) return launch_col_from<I + 1>(idx, W, a, ncols, form, conj_k, s, items, nitems);
         constexpr ColSpec c = kColSpecs[I];
-        const dim3 g(ncols), t(((c.tf + 63) / 64) * 64);
+        const dim3 g(ncols, nitems), t(((c.tf + 63) / 64) * 64);
         const size_t lds = col_lds_bytes<I>();
         if (form == 1)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a);
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a, items);
         else if (conj_k)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a);
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a, items);
         else
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a);
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a, items);
         return hipGetLastError();
     }
 }
 
 hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
-                           hipStream_t s)
+                           hipStream_t s, const BatchItem *items, int nitems)
 {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = col_attrs_from<0>();
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
-    return launch_col_from<0>(idx, W, a, ncols, form, conj_k, s);
+    hipError_t e = set_spec_attributes();
+    if (e != hipSuccess) return e;
+    return launch_col_from<0>(idx, W, a, ncols, form, conj_k, s, items, nitems);
 }
 
 }  // namespace lp
@@ -561,7 +564,8 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // that stay live across iterations.
 template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__restrict__ Rm,
-                                                             float2 *__restrict__ W, RowRegArgs a)
+                                                             float2 *__restrict__ W, RowRegArgs a,
+                                                             const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
     using F0 = RegPass<M, R0, 1, TF, B, 0>;
@@ -570,6 +574,13 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     const int tid0 = threadIdx.x;
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        Rm = it.in;
+        W = it.w;
+        a.ny = it.ny;
+        a.nx = it.nx;
+    }
     const int ntiles = (a.ny + B - 1) / B;
     const int G = gridDim.x;
     const int64_t ny = a.ny;
@@ -691,7 +702,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
 // per workgroup as in the forward kernel.
 template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
-                                                             float *__restrict__ Sm, RowRegArgs a)
+                                                             float *__restrict__ Sm, RowRegArgs a,
+                                                             const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
     using I1 = RegPass<M, R1, R2, TF, B, R2>;
@@ -700,6 +712,13 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     const int tid0 = threadIdx.x;
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        W = it.w;
+        Sm = it.out;
+        a.ny = it.ny;
+        a.nx = it.nx;
+    }
     const int ntiles = (a.ny + B - 1) / B;
     const int G = gridDim.x;
     const int64_t ny = a.ny;
@@ -888,12 +907,12 @@ static hipError_t row_attrs()
 
 template <int I>
 static hipError_t launch_row_from(int idx, const void *in, void *out, const RowRegArgs &a, bool fwd,
-                                  hipStream_t s)
+                                  hipStream_t s, const BatchItem *items, int nitems)
 {
     if constexpr (I >= kNumRowSpecs) {
         return hipErrorInvalidValue;
     } else {
-        if (idx != I) return launch_row_from<I + 1>(idx, in, out, a, fwd, s);
+        if (idx != I) return launch_row_from<I + 1>(idx, in, out, a, fwd, s, items, nitems);
         constexpr RowSpec c = kRowSpecs[I];
         constexpr int PF = c.pf;
         const int ntiles = (a.ny + c.b - 1) / c.b;
@@ -912,36 +931,50 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
             }
             groups = ntiles < r ? ntiles : r;
         }
-        const dim3 g(groups), t(c.tf * c.b);
+        const dim3 g(groups, nitems), t(c.tf * c.b);
         const size_t lds = row_lds_bytes<I>();
         const bool even = (a.nx % 2) == 0;
         if (fwd) {
             const float *R = static_cast<const float *>(in);
             float2 *W = static_cast<float2 *>(out);
-            if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, R, W, a);
-            else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, R, W, a);
+            if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, R, W, a, items);
+            else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, R, W, a, items);
         } else {
             const float2 *W = static_cast<const float2 *>(in);
             float *S = static_cast<float *>(out);
-            if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, W, S, a);
-            else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, W, S, a);
+            if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, W, S, a, items);
+            else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, W, S, a, items);
         }
         return hipGetLastError();
     }
 }
 
-hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s)
+hipError_t launch_rows_r2c_reg(const float *R, float2 *W, const RowRegArgs &a, int idx, hipStream_t s,
+                               const BatchItem *items, int nitems)
 {
-    hipError_t e = row_attrs();
+    hipError_t e = set_spec_attributes();
     if (e != hipSuccess) return e;
-    return launch_row_from<0>(idx, R, W, a, true, s);
+    return launch_row_from<0>(idx, R, W, a, true, s, items, nitems);
 }
 
-hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s)
+hipError_t launch_rows_c2r_reg(const float2 *W, float *S, const RowRegArgs &a, int idx, hipStream_t s,
+                               const BatchItem *items, int nitems)
 {
-    hipError_t e = row_attrs();
+    hipError_t e = set_spec_attributes();
     if (e != hipSuccess) return e;
-    return launch_row_from<0>(idx, W, S, a, false, s);
+    return launch_row_from<0>(idx, W, S, a, false, s, items, nitems);
+}
+
+// Dynamic-LDS limits of every specialised kernel, set once (before any graph
+// capture: this is not a stream operation).
+hipError_t set_spec_attributes()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = col_attrs_from<0>();
+    if (e == hipSuccess) e = row_attrs();
+    if (e == hipSuccess) done = true;
+    return e;
 }
 
 }  // namespace lp

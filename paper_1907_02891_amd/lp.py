@@ -60,6 +60,18 @@ _SIGS = {
     "lp_plan_get_variant": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_set_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "lp_plan_variant_info": ([_vp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
+    "lp_batch_create": ([ctypes.c_int, _i64p, _i64p, _ip, ctypes.c_int, _i64p, _i64p, ctypes.c_double], _vp),
+    "lp_batch_destroy": ([_vp], None),
+    "lp_batch_workspace_bytes": ([_vp], ctypes.c_size_t),
+    "lp_batch_bind": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "lp_batch_kernel_spectra": ([_vp, ctypes.POINTER(_dp)], ctypes.c_int),
+    "lp_convolve_batched": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)], ctypes.c_int),
+    "lp_batch_use_graph": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_batch_group_count": ([_vp], ctypes.c_int),
+    "lp_batch_group_info": ([_vp, ctypes.c_int, _i64p, ctypes.c_int], ctypes.c_int),
+    "lp_batch_tile_group": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_batch_set_variant": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "lp_batch_get_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -237,6 +249,94 @@ class Plan:
         calls = ctypes.c_int()
         _check(_lib.lp_plan_stage_ms(self._p, ms, 3, ctypes.byref(calls)))
         return list(ms), calls.value
+
+
+class Batch:
+    """Many maps with a few kernels (lp_batch_*): tiles x bands."""
+
+    def __init__(self, shapes, psf_ids, psf_shapes, pitch_km=0.5):
+        n = len(shapes)
+        ny = (ctypes.c_int64 * n)(*[int(s[0]) for s in shapes])
+        nx = (ctypes.c_int64 * n)(*[int(s[1]) for s in shapes])
+        ids = (ctypes.c_int * n)(*[int(i) for i in psf_ids])
+        npsf = len(psf_shapes)
+        ky = (ctypes.c_int64 * npsf)(*[int(s[0]) for s in psf_shapes])
+        kx = (ctypes.c_int64 * npsf)(*[int(s[1]) for s in psf_shapes])
+        self._b = _lib.lp_batch_create(n, ny, nx, ids, npsf, ky, kx, float(pitch_km))
+        if not self._b:
+            raise LPError(_lib.lp_last_status(), last_error())
+        self.shapes = [(int(a), int(b)) for a, b in shapes]
+        self.psf_shapes = [tuple(p) for p in psf_shapes]
+        self.workspace = None
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _lib.lp_batch_destroy(self._b)
+            self._b = None
+
+    __del__ = close
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.lp_batch_workspace_bytes(self._b))
+
+    def bind(self, device=None, stream=None):
+        import torch
+        dev = torch.device("cuda") if device is None else torch.device(device)
+        ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        ptr = ws.data_ptr()
+        off = (-ptr) % 256
+        self.workspace = ws
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        _check(_lib.lp_batch_bind(self._b, ctypes.c_void_p(ptr + off), ws.numel() - off,
+                                  _stream_ptr(self.stream)))
+        return self
+
+    def set_kernels(self, psfs):
+        arrs = [np.ascontiguousarray(p, dtype=np.float64) for p in psfs]
+        for a, sh in zip(arrs, self.psf_shapes):
+            if a.shape != sh:
+                raise ValueError(f"kernel shape {a.shape} != {sh}")
+        ptrs = (_dp * len(arrs))(*[a.ctypes.data_as(_dp) for a in arrs])
+        _check(_lib.lp_batch_kernel_spectra(self._b, ptrs))
+        self._psfs = arrs
+        return self
+
+    def convolve(self, maps, outs=None):
+        """maps: list of contiguous float32 CUDA tensors (shape per map)."""
+        import torch
+        if outs is None:
+            outs = [torch.empty_like(m) for m in maps]
+        for m, o, sh in zip(maps, outs, self.shapes):
+            if tuple(m.shape) != sh or tuple(o.shape) != sh or m.dtype != torch.float32 or not m.is_contiguous():
+                raise ValueError("bad map tensor")
+        n = len(self.shapes)
+        ins = (_vp * n)(*[m.data_ptr() for m in maps])
+        ous = (_vp * n)(*[o.data_ptr() for o in outs])
+        _check(_lib.lp_convolve_batched(self._b, ins, ous))
+        return outs
+
+    def use_graph(self, enable=True):
+        _check(_lib.lp_batch_use_graph(self._b, int(bool(enable))))
+
+    @property
+    def groups(self):
+        out = []
+        for g in range(_lib.lp_batch_group_count(self._b)):
+            v = (ctypes.c_int64 * 6)()
+            _check(_lib.lp_batch_group_info(self._b, g, v, 6))
+            out.append({"padding": (v[0], v[1]), "maps": v[2], "row_variants": v[3],
+                        "column_variants": v[4], "max_ny": v[5]})
+        return out
+
+    def tile_group(self, t):
+        return int(_lib.lp_batch_tile_group(self._b, int(t)))
+
+    def set_variant(self, g, stage, k):
+        _check(_lib.lp_batch_set_variant(self._b, int(g), int(stage), int(k)))
+
+    def variant(self, g, stage):
+        return int(_lib.lp_batch_get_variant(self._b, int(g), int(stage)))
 
 
 def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO):

@@ -139,3 +139,28 @@ def test_shape_choice_fits_lds():
         assert c >= 1 and b >= 1 and (c & (c - 1)) == 0 and (b & (b - 1)) == 0
         assert py * c * 8 <= 163840
         assert (px // 2 + 1) * b * 8 <= 163840
+
+
+def test_batch_contract_errors():
+    with pytest.raises(lp.LPError) as ei:
+        lp.Batch([(100, 100)], [0], [(30000, 3)])
+    assert ei.value.code == lp.LP_E_SIZE
+    with pytest.raises(lp.LPError) as ei:
+        lp.Batch([(100, 100)], [2], [(5, 5)])
+    assert ei.value.code == lp.LP_E_INVALID
+    with pytest.raises(lp.LPError) as ei:
+        lp.Batch([(0, 100)], [0], [(5, 5)])
+    assert ei.value.code == lp.LP_E_INVALID
+    b = lp.Batch([(600, 700), (100, 100), (600, 700)], [0, 1, 1], [(101, 101), (5, 5)])
+    assert b.workspace_bytes > 0
+    gs = b.groups
+    assert sum(g["maps"] for g in gs) == 3
+    for g in gs:
+        py, px = g["padding"]
+        assert py >= 1 and px % 2 == 0 and g["row_variants"] >= 1 and g["column_variants"] >= 1
+    assert b.tile_group(0) == b.tile_group(2) != b.tile_group(1)
+    lib = lp.raw()
+    fake = (ctypes.c_void_p * 3)(256, 256, 256)
+    assert lib.lp_convolve_batched(b._b, fake, fake) == lp.LP_E_NOMEM
+    assert lib.lp_batch_set_variant(b._b, 0, 7, 0) == lp.LP_E_INVALID
+    assert lib.lp_batch_set_variant(b._b, 0, lp.STAGE_ROWS, 99) == lp.LP_E_INVALID

@@ -255,12 +255,17 @@ def bench_batched(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    t0 = time.perf_counter()
-    b = lp.Batch(shapes, ids, [p.shape for p in psfs]).bind(device=dev, stream=stream)
-    b.set_kernels(psfs)
-    t_setup = time.perf_counter() - t0
     xs = [torch.from_numpy(m).to(dev) for m in maps]
     ys = [torch.empty_like(x) for x in xs]
+    t0 = time.perf_counter()
+    tune_report = None
+    if args.no_tune:
+        b = lp.Batch(shapes, ids, [p.shape for p in psfs]).bind(device=dev, stream=stream)
+        b.set_kernels(psfs)
+    else:
+        from paper_1907_02891_amd import tune
+        b, tune_report = tune.autotune_batch(shapes, ids, psfs, xs)
+    t_setup = time.perf_counter() - t0
     for _ in range(args.warmup):
         b.convolve(xs, ys)
     torch.cuda.synchronize()
@@ -279,7 +284,8 @@ def bench_batched(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched-64tiles-3bands-4psf1201", "maps": len(maps), "output_px": npx,
                    "classes": [g["padding"] for g in b.groups]},
-        "setup_s": {"inputs": round(t_gen, 2), "batch_and_spectra": round(t_setup, 3)},
+        "setup_s": {"inputs": round(t_gen, 2), "batch_spectra_and_autotune": round(t_setup, 3)},
+        "autotune": [{"classes": r["classes"], "ms": round(r["ms"], 4)} for r in (tune_report or [])],
     }
     if args.check > 0:
         rng = np.random.default_rng(6)

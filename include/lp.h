@@ -197,6 +197,21 @@ int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group)
 lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx,
                           const int *psf_id, int n_psf, const int64_t *ky,
                           const int64_t *kx, double pitch_km);
+/* As lp_batch_create, with the candidate padded lengths restricted to the
+ * given lists (column axis: lengths_y, row axis: lengths_x; an empty list
+ * keeps every specialised length).  Fewer, larger classes mean fewer and
+ * fuller launches at the cost of more padding: the autotuner picks.  A length
+ * without specialised kernels is LP_E_SIZE. */
+lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *nx,
+                                 const int *psf_id, int n_psf, const int64_t *ky,
+                                 const int64_t *kx, double pitch_km,
+                                 const int64_t *lengths_y, int n_ly,
+                                 const int64_t *lengths_x, int n_lx);
+
+/* The specialised padded lengths: axis 0 columns (Py), axis 1 rows (Px).
+ * Writes up to n into out; returns how many exist. */
+int lp_batch_spec_lengths(int axis, int64_t *out, int n);
+
 void lp_batch_destroy(lp_batch *batch);
 size_t lp_batch_workspace_bytes(const lp_batch *batch);
 

@@ -884,6 +884,13 @@ extern "C" {
 lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
                           const int64_t *ky, const int64_t *kx, double pitch_km)
 {
+    return lp_batch_create_padded(n_tiles, ny, nx, psf_id, n_psf, ky, kx, pitch_km, nullptr, 0, nullptr, 0);
+}
+
+lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
+                                 const int64_t *ky, const int64_t *kx, double pitch_km, const int64_t *lengths_y,
+                                 int n_ly, const int64_t *lengths_x, int n_lx)
+{
     clear_error();
     if (n_tiles <= 0 || n_psf <= 0 || !ny || !nx || !psf_id || !ky || !kx) {
         fail(LP_E_INVALID, "batch: empty or null arguments");
@@ -898,7 +905,30 @@ lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx, con
             fail(LP_E_INVALID, "kernel %d has a non-positive size", p);
             return nullptr;
         }
-    const std::vector<int64_t> ly = spec_lengths(true), lx = spec_lengths(false);
+    std::vector<int64_t> ly = spec_lengths(true), lx = spec_lengths(false);
+    if (n_ly > 0 || n_lx > 0) {
+        if ((n_ly > 0 && !lengths_y) || (n_lx > 0 && !lengths_x) || n_ly < 0 || n_lx < 0) {
+            fail(LP_E_INVALID, "batch: null or negative length lists");
+            return nullptr;
+        }
+        auto restrict_to = [](std::vector<int64_t> &all, const int64_t *want, int n, const char *axis) {
+            std::vector<int64_t> keep;
+            for (int i = 0; i < n; ++i) {
+                if (std::find(all.begin(), all.end(), want[i]) == all.end()) {
+                    fail(LP_E_SIZE, "batch: %s length %lld has no specialised kernels", axis, (long long)want[i]);
+                    return false;
+                }
+                keep.push_back(want[i]);
+            }
+            std::sort(keep.begin(), keep.end());
+            keep.erase(std::unique(keep.begin(), keep.end()), keep.end());
+            all = keep;
+            return true;
+        };
+        if ((n_ly > 0 && !restrict_to(ly, lengths_y, n_ly, "column")) ||
+            (n_lx > 0 && !restrict_to(lx, lengths_x, n_lx, "row")))
+            return nullptr;
+    }
     lp_batch *b = new (std::nothrow) lp_batch();
     if (!b) {
         fail(LP_E_NOMEM, "out of host memory");
@@ -1166,6 +1196,13 @@ int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const 
     }
     if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return fail_hip(e, "graph launch");
     return LP_OK;
+}
+
+int lp_batch_spec_lengths(int axis, int64_t *out, int n)
+{
+    const std::vector<int64_t> v = spec_lengths(axis == 0);
+    for (int i = 0; i < n && i < static_cast<int>(v.size()); ++i) out[i] = v[i];
+    return static_cast<int>(v.size());
 }
 
 int lp_batch_use_graph(lp_batch *b, int enable)

@@ -61,6 +61,9 @@ _SIGS = {
     "lp_plan_set_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "lp_plan_variant_info": ([_vp, ctypes.c_int, ctypes.c_int, _ip, ctypes.c_int], ctypes.c_int),
     "lp_batch_create": ([ctypes.c_int, _i64p, _i64p, _ip, ctypes.c_int, _i64p, _i64p, ctypes.c_double], _vp),
+    "lp_batch_create_padded": ([ctypes.c_int, _i64p, _i64p, _ip, ctypes.c_int, _i64p, _i64p, ctypes.c_double,
+                                _i64p, ctypes.c_int, _i64p, ctypes.c_int], _vp),
+    "lp_batch_spec_lengths": ([ctypes.c_int, _i64p, ctypes.c_int], ctypes.c_int),
     "lp_batch_destroy": ([_vp], None),
     "lp_batch_workspace_bytes": ([_vp], ctypes.c_size_t),
     "lp_batch_bind": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
@@ -254,7 +257,9 @@ class Plan:
 class Batch:
     """Many maps with a few kernels (lp_batch_*): tiles x bands."""
 
-    def __init__(self, shapes, psf_ids, psf_shapes, pitch_km=0.5):
+    def __init__(self, shapes, psf_ids, psf_shapes, pitch_km=0.5, lengths=None):
+        """lengths: optional (column lengths, row lengths) the padding classes
+        may use (subsets of spec_lengths())."""
         n = len(shapes)
         ny = (ctypes.c_int64 * n)(*[int(s[0]) for s in shapes])
         nx = (ctypes.c_int64 * n)(*[int(s[1]) for s in shapes])
@@ -262,7 +267,13 @@ class Batch:
         npsf = len(psf_shapes)
         ky = (ctypes.c_int64 * npsf)(*[int(s[0]) for s in psf_shapes])
         kx = (ctypes.c_int64 * npsf)(*[int(s[1]) for s in psf_shapes])
-        self._b = _lib.lp_batch_create(n, ny, nx, ids, npsf, ky, kx, float(pitch_km))
+        if lengths is None:
+            self._b = _lib.lp_batch_create(n, ny, nx, ids, npsf, ky, kx, float(pitch_km))
+        else:
+            ly = (ctypes.c_int64 * max(1, len(lengths[0])))(*lengths[0])
+            lx = (ctypes.c_int64 * max(1, len(lengths[1])))(*lengths[1])
+            self._b = _lib.lp_batch_create_padded(n, ny, nx, ids, npsf, ky, kx, float(pitch_km),
+                                                  ly, len(lengths[0]), lx, len(lengths[1]))
         if not self._b:
             raise LPError(_lib.lp_last_status(), last_error())
         self.shapes = [(int(a), int(b)) for a, b in shapes]
@@ -337,6 +348,17 @@ class Batch:
 
     def variant(self, g, stage):
         return int(_lib.lp_batch_get_variant(self._b, int(g), int(stage)))
+
+
+def spec_lengths():
+    """(column lengths, row lengths) that have specialised kernels."""
+    out = []
+    for axis in (0, 1):
+        n = _lib.lp_batch_spec_lengths(axis, None, 0)
+        v = (ctypes.c_int64 * n)()
+        _lib.lp_batch_spec_lengths(axis, v, n)
+        out.append(list(v))
+    return tuple(out)
 
 
 def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO):

@@ -100,3 +100,76 @@ def autotune(plan, x=None, out=None, *, reps=20, warmup=3, use_cache=True, verbo
     if use_cache:
         _save_cache(cache)
     return report
+
+
+def _time_batch(b, xs, ys, reps, warmup):
+    import torch
+    for _ in range(warmup):
+        b.convolve(xs, ys)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        b.convolve(xs, ys)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def length_sets(need_min, need_max, all_lengths):
+    """Candidate restrictions of the padded-length set between the smallest
+    length >= need_min and the smallest length >= need_max (which is always
+    kept): the full range, every second / third length, the top few."""
+    L = sorted(all_lengths)
+    cap = min([x for x in L if x >= need_max] or [L[-1]])
+    lo = min([x for x in L if x >= need_min] or [cap])
+    L = [x for x in L if lo <= x <= cap]
+    cands = [L]
+    for step in (2, 3):
+        for start in range(step):
+            cands.append(sorted(set(L[start::step]) | {cap}))
+    for k in (1, 2, 3):
+        cands.append(L[-k:])
+    out, seen = [], set()
+    for c in cands:
+        t = tuple(c)
+        if t not in seen:
+            seen.add(t)
+            out.append(list(c))
+    return out
+
+
+def autotune_batch(shapes, psf_ids, psfs, maps, *, pitch_km=0.5, reps=3, warmup=1, verbose=False):
+    """Choose the padding classes of a batch: try restricted length sets
+    (fewer, larger classes versus more padding), time each batch on the
+    given maps (device tensors), return (best Batch, report)."""
+    import torch
+    ly_all, lx_all = lp.spec_lengths()
+    ky = [p.shape[0] for p in psfs]
+    kx = [p.shape[1] for p in psfs]
+    need = [(s[0] + ky[i] - 1, s[1] + kx[i] - 1) for s, i in zip(shapes, psf_ids)]
+    sets_y = length_sets(min(n[0] for n in need), max(n[0] for n in need), ly_all)
+    sets_x = length_sets(min(n[1] for n in need), max(n[1] for n in need), lx_all)
+    ys = [torch.empty_like(m) for m in maps]
+    best, report = None, []
+    # the same thinning policy on both axes (the k-th candidate of each)
+    for k in range(max(len(sets_y), len(sets_x))):
+        sy, sx = sets_y[min(k, len(sets_y) - 1)], sets_x[min(k, len(sets_x) - 1)]
+        try:
+            b = lp.Batch(shapes, psf_ids, [p.shape for p in psfs], pitch_km, lengths=(sy, sx)).bind()
+        except lp.LPError:
+            continue
+        b.set_kernels(psfs)
+        ms = _time_batch(b, maps, ys, reps, warmup)
+        report.append({"lengths_y": sy, "lengths_x": sx, "classes": len(b.groups), "ms": ms})
+        if verbose:
+            print(f"tune batch: {len(b.groups)} classes, {ms:.3f} ms  y={sy} x={sx}", flush=True)
+        if best is None or ms < best[0]:
+            if best is not None:
+                best[1].close()
+            best = (ms, b)
+        else:
+            b.close()
+        torch.cuda.empty_cache()
+    return best[1], report

@@ -103,6 +103,13 @@ def cpu_baseline(R, K, budget_s):
                       f"over the {K.shape[0]}x{K.shape[1]} kernel, {dt:.1f} s"}
 
 
+PRECISIONS = {"fp32": (0, "f32", "FP32 FFT convolution"),
+              "fp16x2": (1, "f16x2 split, f32 accumulate",
+                         "FFT convolution, radix-16 passes on MFMA with FP16 hi+lo operands"),
+              "bf16x3": (2, "bf16x3 split, f32 accumulate",
+                         "FFT convolution, radix-16 passes on MFMA with BF16 x3 operands")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +123,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (variant 0 of each stage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte calibration)")
+    ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS),
+                    help="transform arithmetic: FP32 vector ALU, or radix-16 passes on the "
+                         "matrix cores with FP16 hi+lo / BF16 x3 split operands")
+    ap.add_argument("--kernels", default="auto", choices=["auto", "generic"],
+                    help="generic: LDS-staged kernels only (no specialised register kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -137,6 +149,10 @@ def main():
 
     t0 = time.perf_counter()
     plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=(wl.py, wl.px))
+    mode, dtype, what = PRECISIONS[args.precision]
+    plan.set_precision(mode)
+    if args.kernels == "generic":
+        plan.set_kernels(lp.KERNELS_GENERIC)
     plan.bind(device=dev, stream=stream)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
@@ -148,7 +164,7 @@ def main():
     y = torch.empty_like(x)
     t0 = time.perf_counter()
     tuning = None
-    if not args.no_tune:
+    if not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
         from paper_1907_02891_amd import tune
         tuning = tune.autotune(plan, x, y, use_cache=False)
     t_tune = time.perf_counter() - t0
@@ -184,17 +200,19 @@ def main():
                 "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}
 
     out = {
-        "metric": "output pixels/s per MI355X (FP32 FFT convolution) at rel-L2 <= 1e-5",
+        "metric": f"output pixels/s per MI355X ({what}) at rel-L2 <= 1e-5",
         "value": ny * nx / (ms_step * 1e-3),
         "unit": "output pixels/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": dtype, "data": "synthetic",
         "config": {"workload": wl.name, "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
                    "padding": [py, px], "pitch_km": wl.pitch_km,
                    "spectrum_form": {1: "real-quadrant", 2: "complex"}[plan.form],
-                   "cols_per_group": plan.shape[0], "rows_per_group": plan.shape[1]},
+                   "cols_per_group": plan.shape[0], "rows_per_group": plan.shape[1],
+                   "precision": args.precision,
+                   "kernels": "specialised" if plan.kernels == lp.KERNELS_SPECIALISED else "generic"},
         "roofline": roofline,
         "path": {"stage_ms": [round(s, 5) for s in stage_avg],
                  "stage_names": ["rows forward", "columns", "rows inverse"],
@@ -207,7 +225,7 @@ def main():
         "variants": {lp_stage: {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
                                 "tried_ms": [round(t, 5) for t in (tuning or {}).get(lp_stage, {}).get("all", [])]}
                      for lp_stage, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS))
-                     if plan.variant_count(st) > 0},
+                     if plan.variant_count(st) > 0 and plan.kernels == lp.KERNELS_SPECIALISED},
         "kernel_source": src_hash,
     }
 
@@ -278,7 +296,7 @@ def bench_batched(args):
     ms_step = ev0.elapsed_time(ev1) / args.steps
     npx = sum(a * c for a, c in shapes)
     out = {
-        "metric": "output pixels/s per MI355X (FP32 FFT convolution) at rel-L2 <= 1e-5",
+        "metric": f"output pixels/s per MI355X ({what}) at rel-L2 <= 1e-5",
         "value": npx / (ms_step * 1e-3), "unit": "output pixels/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -184,6 +184,27 @@ int lp_plan_variant_info(const lp_plan *plan, int stage, int k, int *info, int n
  * workgroup of the column stage, rows per workgroup of the row stages. */
 int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);
 
+/* Arithmetic of the transforms (the DFTs of Eq. 10 inside Eq. 9).
+ * LP_PRECISION_FP32 (default): every butterfly on the vector ALU in FP32.
+ * The split forms factor each transform length with as many radix-16 passes
+ * as its power of two allows and run those passes as dense 32 x 32 real
+ * matrix products on the matrix cores (v_mfma_f32_16x16x32, FP32
+ * accumulation), with both operands split into low-precision terms:
+ *   LP_PRECISION_SPLIT_FP16: x = hi + lo in FP16 after scaling each
+ *     butterfly's 16 inputs by a power of two (largest in [2^14, 2^15)), the
+ *     matrix by 2^14; three products hi*hi + hi*lo + lo*hi;
+ *   LP_PRECISION_SPLIT_BF16: x = x1 + x2 + x3 in BF16, six products (all
+ *     terms of total order <= 4).
+ * Both keep the dropped terms near 2^-22 of a butterfly's largest input, so
+ * the result stays at FP32-level error.  A split plan runs the generic
+ * LDS-staged kernels (the specialised ones are FP32 only); lengths without
+ * a factor 16 get no matrix pass.  Set before lp_plan_bind (LP_E_STATE
+ * after); unknown mode: LP_E_INVALID.  lp_plan_precision returns the mode
+ * (-1 for a NULL plan). */
+enum { LP_PRECISION_FP32 = 0, LP_PRECISION_SPLIT_FP16 = 1, LP_PRECISION_SPLIT_BF16 = 2 };
+int lp_plan_set_precision(lp_plan *plan, int mode);
+int lp_plan_precision(const lp_plan *plan);
+
 /* ---------------------------------------------------------------- batch --
  * Many independent maps (tiles, spectral bands) convolved with a few kernels:
  * the factorable-classes case of Sec. 2.2 (Eq. 4), handled map by map.  Map t

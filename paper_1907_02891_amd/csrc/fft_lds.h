@@ -184,23 +184,6 @@ __device__ __forceinline__ void stockham_pass(float2 *buf, const FftPass &P, int
     __syncthreads();
 }
 
-// Whole transform: all passes of `d` in order.  Entry and exit are barriers.
-template <bool INV>
-__device__ void lds_fft(float2 *buf, const FftDesc &d, int logb, const float2 *__restrict__ tw,
-                        int tid, int nt)
-{
-    for (int ps = 0; ps < d.npass; ++ps) {
-        const FftPass P = d.pass[ps];
-        switch (P.radix) {
-            case 8: stockham_pass<8, INV>(buf, P, logb, tw, tid, nt); break;
-            case 4: stockham_pass<4, INV>(buf, P, logb, tw, tid, nt); break;
-            case 5: stockham_pass<5, INV>(buf, P, logb, tw, tid, nt); break;
-            case 3: stockham_pass<3, INV>(buf, P, logb, tw, tid, nt); break;
-            default: stockham_pass<2, INV>(buf, P, logb, tw, tid, nt); break;
-        }
-    }
-}
-
 // The same value in a register the optimiser cannot see through: index
 // arithmetic derived from it inside a loop is recomputed per iteration instead
 // of being hoisted into registers that stay live across the whole loop.
@@ -208,6 +191,282 @@ __device__ __forceinline__ int opaque_v(int v)
 {
     asm volatile("" : "+v"(v));
     return v;
+}
+
+// ------------------------------------------------- radix 16 on matrix cores
+// A radix-16 pass as a dense product on MFMA with split operands and FP32
+// accumulation.  In real form the 16-point DFT maps the 32 reals
+// (Re x_j, Im x_j) to the 32 reals (Re y_k, Im y_k); v_mfma_f32_16x16x32
+// takes one 16 x 32 tile of that matrix (the Re y rows, or the Im y rows)
+// times 16 butterflies.  Lane l of a wave works on butterfly l % 16 and holds
+// inputs j = 4 g + t, t < 4, g = l / 16, as the K index 8 g + 2 t + (0 re,
+// 1 im); the instruction leaves it outputs k = 4 g + t of the same butterfly.
+// SPLIT 1: FP16 hi + lo for both operands (3 products per tile); each
+// butterfly's inputs are scaled by a power of two so the largest lies in
+// [2^14, 2^15), the matrix by 2^14.  SPLIT 2: BF16 x1 + x2 + x3 (6 products
+// per tile, terms of total order <= 4).  Dropped terms are near 2^-22
+// relative to the butterfly's largest input.
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+typedef unsigned u4v_t __attribute__((ext_vector_type(4)));  // one 16-byte fragment
+
+// cos(2 pi m / 16), correctly rounded, by selects (no indexed local array,
+// which would live in scratch memory).
+__device__ __forceinline__ float cos16(int m)
+{
+    m &= 15;
+    const int f = (m > 8) ? 16 - m : m;  // cos is even: fold to [0, 8]
+    const int q = (f > 4) ? 8 - f : f;   // cos(pi - x) = -cos(x): fold to [0, 4]
+    const float v = (q == 0) ? 1.f
+                  : (q == 1) ? 0.923879532511286756128183189396788933f   // cos(pi/8)
+                  : (q == 2) ? 0.707106781186547524400844362104849039f   // cos(pi/4)
+                  : (q == 3) ? 0.382683432365089771728459984030398867f   // cos(3pi/8)
+                             : 0.f;
+    return (f > 4) ? -v : v;
+}
+
+template <int SPLIT>
+struct MfmaOps;
+
+template <>
+struct MfmaOps<1> {
+    half8_t ah[2], al[2];  // [0]: Re y rows, [1]: Im y rows
+    static constexpr float kMatScale = 16384.f;  // 2^14
+    static constexpr int kVecs = 4;              // 16-byte fragments per lane
+    __device__ __forceinline__ void load(const u4v_t *f, int lane)
+    {
+        ah[0] = __builtin_bit_cast(half8_t, f[lane]);
+        ah[1] = __builtin_bit_cast(half8_t, f[64 + lane]);
+        al[0] = __builtin_bit_cast(half8_t, f[128 + lane]);
+        al[1] = __builtin_bit_cast(half8_t, f[192 + lane]);
+    }
+    __device__ __forceinline__ void store(u4v_t *f, int lane) const
+    {
+        f[lane] = __builtin_bit_cast(u4v_t, ah[0]);
+        f[64 + lane] = __builtin_bit_cast(u4v_t, ah[1]);
+        f[128 + lane] = __builtin_bit_cast(u4v_t, al[0]);
+        f[192 + lane] = __builtin_bit_cast(u4v_t, al[1]);
+    }
+    __device__ __forceinline__ void set_matrix(const float (&m)[2][8])
+    {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float x = m[r][q] * kMatScale;
+                ah[r][q] = static_cast<_Float16>(x);
+                al[r][q] = static_cast<_Float16>(x - static_cast<float>(ah[r][q]));
+            }
+    }
+    __device__ __forceinline__ void product(const float (&x)[8], f4v_t &dre, f4v_t &dim) const
+    {
+        half8_t h, l;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            h[q] = static_cast<_Float16>(x[q]);
+            l[q] = static_cast<_Float16>(x[q] - static_cast<float>(h[q]));
+        }
+        f4v_t d0 = {}, d1 = {};
+        d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], h, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], h, d1, 0, 0, 0);
+        d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], l, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], l, d1, 0, 0, 0);
+        d0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[0], h, d0, 0, 0, 0);
+        d1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[1], h, d1, 0, 0, 0);
+        dre = d0;
+        dim = d1;
+    }
+};
+
+template <>
+struct MfmaOps<2> {
+    bf8_t a[2][3];
+    static constexpr float kMatScale = 1.f;
+    static constexpr int kVecs = 6;
+    __device__ __forceinline__ void load(const u4v_t *f, int lane)
+    {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) a[v / 3][v % 3] = __builtin_bit_cast(bf8_t, f[64 * v + lane]);
+    }
+    __device__ __forceinline__ void store(u4v_t *f, int lane) const
+    {
+#pragma unroll
+        for (int v = 0; v < 6; ++v) f[64 * v + lane] = __builtin_bit_cast(u4v_t, a[v / 3][v % 3]);
+    }
+    __device__ __forceinline__ static void split3(const float (&x)[8], bf8_t (&t)[3])
+    {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const __bf16 t1 = static_cast<__bf16>(x[q]);
+            const float r1 = x[q] - static_cast<float>(t1);
+            const __bf16 t2 = static_cast<__bf16>(r1);
+            t[0][q] = t1;
+            t[1][q] = t2;
+            t[2][q] = static_cast<__bf16>(r1 - static_cast<float>(t2));
+        }
+    }
+    __device__ __forceinline__ void set_matrix(const float (&m)[2][8])
+    {
+        split3(m[0], a[0]);
+        split3(m[1], a[1]);
+    }
+    __device__ __forceinline__ void product(const float (&x)[8], f4v_t &dre, f4v_t &dim) const
+    {
+        bf8_t t[3];
+        split3(x, t);
+        f4v_t d0 = {}, d1 = {};
+        // terms a_u x_v with u + v <= 4 (1-based): 11 12 21 13 22 31
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3 - u; ++v) {
+                d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][u], t[v], d0, 0, 0, 0);
+                d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][u], t[v], d1, 0, 0, 0);
+            }
+        dre = d0;
+        dim = d1;
+    }
+};
+
+// This lane's slices of the two 16 x 32 tiles of the real DFT matrix: row
+// k = lane % 16, K index 8 (lane / 16) + q <-> input j = 4 (lane / 16) + q / 2,
+// real part for even q, imaginary for odd q.
+template <int SPLIT, bool INV>
+__device__ __forceinline__ void mfma16_matrix(MfmaOps<SPLIT> &ops, int lane)
+{
+    const int k = lane & 15, g = lane >> 4;
+    float m[2][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int j = 4 * g + (q >> 1);
+        const float fr = cos16(k * j);                 // Re exp(-+2 pi i k j / 16)
+        const float s = cos16(k * j + 12);             // sin(2 pi k j / 16)
+        const float fi = INV ? s : -s;                 // Im exp(-+2 pi i k j / 16)
+        m[0][q] = (q & 1) ? -fi : fr;                  // Re y = fr xr - fi xi
+        m[1][q] = (q & 1) ? fr : fi;                   // Im y = fi xr + fr xi
+    }
+    ops.set_matrix(m);
+}
+
+// Fragment table of both directions, written once per plan by one wave:
+// [forward | inverse] x kVecs x 64 lanes of 16 bytes.
+template <int SPLIT>
+__device__ __forceinline__ void mfma16_write_fragments(u4v_t *f, int lane)
+{
+    MfmaOps<SPLIT> ops;
+    mfma16_matrix<SPLIT, false>(ops, lane);
+    ops.store(f, lane);
+    mfma16_matrix<SPLIT, true>(ops, lane);
+    ops.store(f + MfmaOps<SPLIT>::kVecs * 64, lane);
+}
+
+// One radix-16 Stockham pass on matrix cores over B = 2^logb interleaved
+// transforms: butterfly w = (i, b) = (w >> logb, w & (B-1)), 16 per wave per
+// chunk, CH chunks per wave.  With at most kEltsPerThread elements per thread
+// the items number at most nt * kEltsPerThread / 16 <= nt * CH / 4.  mf: the
+// fragment table (mfma16_write_fragments).
+template <int SPLIT, bool INV>
+__device__ __forceinline__ void mfma16_pass(float2 *buf, const FftPass &P, int logb,
+                                            const float2 *__restrict__ tw, int tid, int nt,
+                                            const u4v_t *__restrict__ mf)
+{
+    constexpr int CH = (kEltsPerThread + 3) / 4;
+    const int nb = P.nb, p = P.p;
+    const int items = nb << logb;
+    const int bmask = (1 << logb) - 1;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nt >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    MfmaOps<SPLIT> ops;
+    ops.load(mf + (INV ? MfmaOps<SPLIT>::kVecs * 64 : 0), lane);
+    const float unscale0 = 1.f / MfmaOps<SPLIT>::kMatScale;
+    float2 out[CH][4];
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int chunk = wave + ch * nwaves;
+        if (chunk * 16 >= items) break;  // uniform over the wave
+        const int w = chunk * 16 + c;
+        const bool valid = w < items;
+        const int i = w >> logb, b = w & bmask;
+        const int k = (p > 1) ? mod_p(i, p, P.inv_p) : 0;
+        float x[8];
+        float amax = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int j = 4 * g + t;
+            float2 v = make_float2(0.f, 0.f);
+            if (valid) {
+                v = buf[((i + j * nb) << logb) + b];
+                if (p > 1 && j > 0) {
+                    const float2 tj = tw[P.tw + k * 15 + j - 1];
+                    v = INV ? cmulc(v, tj) : cmul(v, tj);
+                }
+            }
+            x[2 * t] = v.x;
+            x[2 * t + 1] = v.y;
+            amax = fmaxf(amax, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+        float unscale = unscale0;
+        if constexpr (SPLIT == 1) {
+            amax = fmaxf(amax, __shfl_xor(amax, 16));
+            amax = fmaxf(amax, __shfl_xor(amax, 32));
+            int e = 0;
+            if (amax > 0.f) {
+                (void)frexpf(amax, &e);  // amax = f 2^e, f in [0.5, 1)
+                e = 15 - e;              // amax 2^(15-e) in [2^14, 2^15)
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = ldexpf(x[q], e);
+            unscale = ldexpf(unscale0, -e);
+        }
+        f4v_t dre, dim;
+        ops.product(x, dre, dim);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) out[ch][t] = make_float2(dre[t] * unscale, dim[t] * unscale);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        const int chunk = wave + ch * nwaves;
+        if (chunk * 16 >= items) break;
+        const int w = chunk * 16 + c;
+        if (w < items) {
+            const int i = w >> logb, b = w & bmask;
+            const int k = (p > 1) ? mod_p(i, p, P.inv_p) : 0;
+            const int base = (i - k) * 16 + k;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) buf[((base + (4 * g + t) * p) << logb) + b] = out[ch][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Whole transform: all passes of `d` in order.  Entry and exit are barriers.
+// SPLIT 0: every pass on the vector ALU in FP32; SPLIT 1 or 2: radix-16
+// passes on matrix cores with split operands (the plan's factorisation
+// then prefers radix 16; mf is the fragment table), the rest as for SPLIT 0.
+// nt is a multiple of 64.
+template <bool INV, int SPLIT = 0>
+__device__ void lds_fft(float2 *buf, const FftDesc &d, int logb, const float2 *__restrict__ tw,
+                        int tid, int nt, const void *mf = nullptr)
+{
+    for (int ps = 0; ps < d.npass; ++ps) {
+        const FftPass P = d.pass[ps];
+        // thread-index arithmetic is redone per pass rather than hoisted out
+        // of the loop into registers live across all passes
+        const int t = opaque_v(tid);
+        switch (P.radix) {
+            case 16:
+                if constexpr (SPLIT != 0)
+                    mfma16_pass<SPLIT, INV>(buf, P, logb, tw, t, nt, static_cast<const u4v_t *>(mf));
+                break;
+            case 8: stockham_pass<8, INV>(buf, P, logb, tw, t, nt); break;
+            case 4: stockham_pass<4, INV>(buf, P, logb, tw, t, nt); break;
+            case 5: stockham_pass<5, INV>(buf, P, logb, tw, t, nt); break;
+            case 3: stockham_pass<3, INV>(buf, P, logb, tw, t, nt); break;
+            default: stockham_pass<2, INV>(buf, P, logb, tw, t, nt); break;
+        }
+    }
 }
 
 // Workgroup index remap so that consecutive logical tiles run on the same XCD

@@ -87,13 +87,22 @@ void exp_frac(int64_t m, int64_t n, double *c, double *s)
 
 // Radix sequence for a 5-smooth length: as many 8s as possible (a trailing
 // 2^1 or 2^2 becomes 4 or 4*4 / 2), then 5s, then 3s.
-std::vector<int> radices(int64_t n)
+std::vector<int> radices(int64_t n, bool prefer16)
 {
     int a = 0, b = 0, c = 0;
     while (n % 2 == 0) { n /= 2; ++a; }
     while (n % 3 == 0) { n /= 3; ++b; }
     while (n % 5 == 0) { n /= 5; ++c; }
     std::vector<int> r;
+    if (prefer16) {
+        // radix-16 passes first (matrix cores), the rest of 2^a as one pass
+        for (int i = 0; i < a / 4; ++i) r.push_back(16);
+        a %= 4;
+        if (a > 0) r.push_back(1 << a);
+        for (int i = 0; i < c; ++i) r.push_back(5);
+        for (int i = 0; i < b; ++i) r.push_back(3);
+        return r;
+    }
     int e8 = a / 3, rem = a % 3;
     if (rem == 1 && e8 > 0) { --e8; rem = 4; }  // 8*2 -> 4*4
     for (int i = 0; i < e8; ++i) r.push_back(8);
@@ -107,11 +116,14 @@ std::vector<int> radices(int64_t n)
 
 // Pass list and FP32 twiddle table (FP64 values rounded once) of a length-n
 // Stockham transform.  The table has n - 1 entries (sum of p * (r - 1)).
-void make_fft(int64_t n, lp::FftDesc *d, std::vector<float> *tw)
+void make_fft(int64_t n, lp::FftDesc *d, std::vector<float> *tw, int split)
 {
     std::memset(d, 0, sizeof *d);
     d->n = static_cast<int32_t>(n);
-    std::vector<int> rs = radices(n);
+    d->split = split;
+    std::vector<int> rs = radices(n, split != 0);
+    // no radix-16 pass: the plain FP32 kernels (fewer registers)
+    if (std::find(rs.begin(), rs.end(), 16) == rs.end()) d->split = 0;
     tw->clear();
     int64_t p = 1;
     for (size_t i = 0; i < rs.size(); ++i) {
@@ -200,6 +212,7 @@ struct lp_plan {
     int col_variant = 0, row_variant = 0;  // k-th specialisation of each length
     size_t twc_max = 2, twr_max = 2;       // table floats reserved (largest variant)
     int variant = 0;  // 0: specialised kernels where available, 1: generic only
+    int precision = LP_PRECISION_FP32;  // split forms run the generic kernels
     std::vector<float> twc;  // its four pass tables, concatenated
     size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
     // register-resident row stages (if the half row length has one)
@@ -207,7 +220,7 @@ struct lp_plan {
     std::vector<float> twr;
     size_t twr_off[4] = {0, 0, 0, 0};
     // workspace layout (byte offsets)
-    size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, off_twr, bytes;
+    size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, off_twr, off_mf, bytes;
     size_t scratch_bytes;
     // binding
     char *ws = nullptr;
@@ -239,7 +252,8 @@ void layout(lp_plan *p)
     p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
     p->off_twc = p->off_twy + align256(p->twy.size() * 4);
     p->off_twr = p->off_twc + align256(p->twc_max * 4);
-    p->bytes = p->off_twr + align256(p->twr_max * 4);
+    p->off_mf = p->off_twr + align256(p->twr_max * 4);
+    p->bytes = p->off_mf + align256(lp::kFragmentBytes);
 }
 
 // Launch shape: C = columns per workgroup of the column stage (a power of
@@ -312,8 +326,8 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     p->px = px;
     p->m = px / 2;
     p->h = p->m + 1;
-    make_fft(p->m, &p->fx, &p->twx);
-    make_fft(p->py, &p->fy, &p->twy);
+    make_fft(p->m, &p->fx, &p->twx, p->precision);
+    make_fft(p->py, &p->fy, &p->twy, p->precision);
     p->col_variant = 0;
     p->row_variant = 0;
     p->twc_max = p->twr_max = 2;
@@ -351,6 +365,7 @@ lp::RowArgs row_args(const lp_plan *p)
     a.fx = p->fx;
     a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twx);
     a.rtw = reinterpret_cast<const float2 *>(p->ws + p->off_rtw);
+    a.mf = p->ws + p->off_mf;
     return a;
 }
 
@@ -365,6 +380,7 @@ lp::ColArgs col_args(const lp_plan *p)
     a.fy = p->fy;
     a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twy);
     a.kh = p->ws + p->off_kh;
+    a.mf = p->ws + p->off_mf;
     return a;
 }
 
@@ -383,7 +399,8 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
     float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
     const lp::RowArgs ra = row_args(p);
     const lp::ColArgs ca = col_args(p);
-    const bool rspec = p->row_spec >= 0 && p->variant == 0;
+    const bool spec_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
+    const bool rspec = p->row_spec >= 0 && spec_ok;
     lp::RowRegArgs rr{};
     if (rspec) {
         const float2 *twr = reinterpret_cast<const float2 *>(p->ws + p->off_twr);
@@ -400,7 +417,7 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
     }
     if (e != hipSuccess) return fail_hip(e, "rows forward launch");
     if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
-    if (p->col_spec >= 0 && p->variant == 0) {
+    if (p->col_spec >= 0 && spec_ok) {
         lp::ColRegArgs cr{};
         const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
         cr.ny = static_cast<int32_t>(p->ny);
@@ -435,7 +452,7 @@ const char *lp_last_error(void) { return g_err.c_str(); }
 
 int lp_last_status(void) { return g_status; }
 
-const char *lp_version(void) { return "lp 0.1 (gfx950, LDS Stockham 2/3/4/5/8)"; }
+const char *lp_version(void) { return "lp 0.2 (gfx950, Stockham 2/3/4/5/8 FP32, radix 16 on MFMA split FP16/BF16)"; }
 
 lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double pitch_km)
 {
@@ -505,10 +522,26 @@ int lp_plan_set_kernels(lp_plan *p, int which)
     return LP_OK;
 }
 
+int lp_plan_set_precision(lp_plan *p, int mode)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (mode != LP_PRECISION_FP32 && mode != LP_PRECISION_SPLIT_FP16 && mode != LP_PRECISION_SPLIT_BF16)
+        return fail(LP_E_INVALID, "unknown precision mode %d", mode);
+    if (p->bound) return fail(LP_E_STATE, "precision must be set before lp_plan_bind");
+    p->precision = mode;
+    // same table sizes (n - 1 twiddles per length), so the layout stands
+    make_fft(p->m, &p->fx, &p->twx, mode);
+    make_fft(p->py, &p->fy, &p->twy, mode);
+    return LP_OK;
+}
+
+int lp_plan_precision(const lp_plan *p) { return p ? p->precision : -1; }
+
 int lp_plan_kernels(const lp_plan *p)
 {
     if (!p) return -1;
-    if (p->variant != 0) return LP_KERNELS_GENERIC;
+    if (p->variant != 0 || p->precision != LP_PRECISION_FP32) return LP_KERNELS_GENERIC;
     return (p->col_spec >= 0 || p->row_spec >= 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
 }
 
@@ -569,7 +602,9 @@ int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
     if (!p) return fail(LP_E_INVALID, "null plan");
     if (cols_per_group) *cols_per_group = 1 << p->logc;
     if (rows_per_group)
-        *rows_per_group = (p->row_spec >= 0 && p->variant == 0) ? lp::row_spec_rows(p->row_spec) : 1 << p->logb;
+        *rows_per_group = (p->row_spec >= 0 && p->variant == 0 && p->precision == LP_PRECISION_FP32)
+                              ? lp::row_spec_rows(p->row_spec)
+                              : 1 << p->logb;
     return LP_OK;
 }
 
@@ -599,6 +634,9 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
             return fail_hip(e, "twiddle upload");
     const int rc = upload_spec_tables(p);
     if (rc != LP_OK) return rc;
+    if (p->precision != LP_PRECISION_FP32 &&
+        (e = lp::launch_mfma_fragments(p->precision, p->ws + p->off_mf, p->stream)) != hipSuccess)
+        return fail_hip(e, "matrix fragment table");
     p->bound = true;
     return LP_OK;
 }

@@ -29,6 +29,7 @@ struct FftPass {
 struct FftDesc {
     int32_t n;
     int32_t npass;
+    int32_t split;  // radix-16 passes on MFMA: 0 none (FP32 VALU), 1 FP16 x2 terms, 2 BF16 x3 terms
     FftPass pass[kMaxPasses];
 };
 
@@ -44,6 +45,7 @@ struct RowArgs {
     FftDesc fx;         // complex transform of length m
     const float2 *tw;   // its twiddles
     const float2 *rtw;  // exp(-2 pi i k / Px), 0 <= k <= m
+    const void *mf;     // matrix-core fragment table (split precision only)
 };
 
 // Column stage arguments (forward transform, spectrum multiply, inverse).
@@ -56,9 +58,15 @@ struct ColArgs {
     FftDesc fy;
     const float2 *tw;
     const void *kh;     // blocked spectrum (float2 complex or float real)
+    const void *mf;     // matrix-core fragment table (split precision only)
 };
 
+// Bytes of the fragment table of the split-precision radix-16 passes (both
+// directions, the larger of the two split forms).
+constexpr size_t kFragmentBytes = 2 * 6 * 64 * 16;
+
 // Launchers (lp_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_mfma_fragments(int split, void *table, hipStream_t s);
 hipError_t launch_rows_r2c(const float *R, float2 *W, const RowArgs &a, int threads,
                            hipStream_t s);
 hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, int threads,

@@ -24,6 +24,7 @@
 namespace lp {
 
 // ------------------------------------------------------------------- rows fwd
+template <int SPLIT>
 __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
                                                    float2 *__restrict__ W, RowArgs a)
 {
@@ -49,7 +50,7 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
         }
     }
     __syncthreads();
-    lds_fft<false>(lds, a.fx, a.logb, a.tw, tid, nt);
+    lds_fft<false, SPLIT>(lds, a.fx, a.logb, a.tw, tid, nt, a.mf);
 
     // X[k] = E[k] + w^k O[k], E = (Z[k] + conj Z[M-k]) / 2,
     // O = -i (Z[k] - conj Z[M-k]) / 2, w = exp(-2 pi i / Px), 0 <= k <= M.
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
 // FORM 1: real even spectrum, one quadrant stored, (py/2+1) rows per block.
 // FORM 2: complex spectrum, py rows per block.  CONJ: use conj(Khat) (the
 // transposed operator).
-template <int FORM, bool CONJ>
+template <int FORM, bool CONJ, int SPLIT>
 __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColArgs a)
 {
     extern __shared__ float2 lds[];
@@ -94,7 +95,7 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
     for (int e = tid; e < total; e += nt)
         lds[e] = (e < stored) ? blk[e] : make_float2(0.f, 0.f);
     __syncthreads();
-    lds_fft<false>(lds, a.fy, a.logc, a.tw, tid, nt);
+    lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
 
     if constexpr (FORM == 1) {
         const float *kq = static_cast<const float *>(a.kh) + static_cast<int64_t>(vb) * (a.ku << a.logc);
@@ -109,12 +110,13 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
             lds[e] = CONJ ? cmulc(lds[e], kc[e]) : cmul(lds[e], kc[e]);
     }
     __syncthreads();
-    lds_fft<true>(lds, a.fy, a.logc, a.tw, tid, nt);
+    lds_fft<true, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
 
     for (int e = tid; e < stored; e += nt) blk[e] = lds[e];
 }
 
 // ------------------------------------------------------------------- rows inv
+template <int SPLIT>
 __global__ void __launch_bounds__(1024) k_rows_c2r(const float2 *__restrict__ W,
                                                    float *__restrict__ S, RowArgs a)
 {
@@ -168,7 +170,7 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(const float2 *__restrict__ W,
         if (k < m) lds[(k << a.logb) + b] = zk;
     }
     __syncthreads();
-    lds_fft<true>(lds, a.fx, a.logb, a.tw, tid, nt);
+    lds_fft<true, SPLIT>(lds, a.fx, a.logb, a.tw, tid, nt, a.mf);
 
     for (int b = 0; b < B; ++b) {
         const int row = row0 + b;
@@ -252,21 +254,59 @@ __global__ void __launch_bounds__(256) k_spec_cols(const double2 *__restrict__ t
             make_float2(static_cast<float>(re * scale), static_cast<float>(im * scale));
 }
 
+// ------------------------------------------------- matrix-core fragments
+template <int SPLIT>
+__global__ void __launch_bounds__(64) k_mfma_fragments(u4v_t *f)
+{
+    mfma16_write_fragments<SPLIT>(f, threadIdx.x);
+}
+
 // ------------------------------------------------------------------ launchers
+hipError_t launch_mfma_fragments(int split, void *table, hipStream_t s)
+{
+    u4v_t *f = static_cast<u4v_t *>(table);
+    if (split == 1) hipLaunchKernelGGL(k_mfma_fragments<1>, dim3(1), dim3(64), 0, s, f);
+    else if (split == 2) hipLaunchKernelGGL(k_mfma_fragments<2>, dim3(1), dim3(64), 0, s, f);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 static size_t row_lds_bytes(const RowArgs &a) { return static_cast<size_t>(a.m + 1) << a.logb << 3; }
 
 hipError_t launch_rows_r2c(const float *R, float2 *W, const RowArgs &a, int threads, hipStream_t s)
 {
-    const int groups = (a.ny + (1 << a.logb) - 1) >> a.logb;
-    hipLaunchKernelGGL(k_rows_r2c, dim3(groups), dim3(threads), row_lds_bytes(a), s, R, W, a);
+    const dim3 g((a.ny + (1 << a.logb) - 1) >> a.logb), t(threads);
+    const size_t lds = row_lds_bytes(a);
+    switch (a.fx.split) {
+        case 1: hipLaunchKernelGGL(k_rows_r2c<1>, g, t, lds, s, R, W, a); break;
+        case 2: hipLaunchKernelGGL(k_rows_r2c<2>, g, t, lds, s, R, W, a); break;
+        default: hipLaunchKernelGGL(k_rows_r2c<0>, g, t, lds, s, R, W, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_rows_c2r(const float2 *W, float *S, const RowArgs &a, int threads, hipStream_t s)
 {
-    const int groups = (a.ny + (1 << a.logb) - 1) >> a.logb;
-    hipLaunchKernelGGL(k_rows_c2r, dim3(groups), dim3(threads), row_lds_bytes(a), s, W, S, a);
+    const dim3 g((a.ny + (1 << a.logb) - 1) >> a.logb), t(threads);
+    const size_t lds = row_lds_bytes(a);
+    switch (a.fx.split) {
+        case 1: hipLaunchKernelGGL(k_rows_c2r<1>, g, t, lds, s, W, S, a); break;
+        case 2: hipLaunchKernelGGL(k_rows_c2r<2>, g, t, lds, s, W, S, a); break;
+        default: hipLaunchKernelGGL(k_rows_c2r<0>, g, t, lds, s, W, S, a); break;
+    }
     return hipGetLastError();
+}
+
+template <int SPLIT>
+static void launch_cols_split(float2 *W, const ColArgs &a, int form, bool conj_k, dim3 g, dim3 t,
+                              size_t lds, hipStream_t s)
+{
+    if (form == 1)
+        hipLaunchKernelGGL((k_cols_conv<1, false, SPLIT>), g, t, lds, s, W, a);
+    else if (conj_k)
+        hipLaunchKernelGGL((k_cols_conv<2, true, SPLIT>), g, t, lds, s, W, a);
+    else
+        hipLaunchKernelGGL((k_cols_conv<2, false, SPLIT>), g, t, lds, s, W, a);
 }
 
 hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, int threads,
@@ -274,12 +314,11 @@ hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, 
 {
     const size_t lds = static_cast<size_t>(a.py) << a.logc << 3;
     const dim3 g(a.nblk), t(threads);
-    if (form == 1)
-        hipLaunchKernelGGL((k_cols_conv<1, false>), g, t, lds, s, W, a);
-    else if (conj_k)
-        hipLaunchKernelGGL((k_cols_conv<2, true>), g, t, lds, s, W, a);
-    else
-        hipLaunchKernelGGL((k_cols_conv<2, false>), g, t, lds, s, W, a);
+    switch (a.fy.split) {
+        case 1: launch_cols_split<1>(W, a, form, conj_k, g, t, lds, s); break;
+        case 2: launch_cols_split<2>(W, a, form, conj_k, g, t, lds, s); break;
+        default: launch_cols_split<0>(W, a, form, conj_k, g, t, lds, s); break;
+    }
     return hipGetLastError();
 }
 
@@ -302,20 +341,29 @@ hipError_t launch_spec_cols(const double2 *t1, int ky, int cy, int py, int ku, i
     return hipGetLastError();
 }
 
-hipError_t set_kernel_attributes()
+template <int SPLIT>
+static hipError_t generic_attributes()
 {
     const void *fns[] = {
-        reinterpret_cast<const void *>(&k_rows_r2c),
-        reinterpret_cast<const void *>(&k_rows_c2r),
-        reinterpret_cast<const void *>(&k_cols_conv<1, false>),
-        reinterpret_cast<const void *>(&k_cols_conv<2, false>),
-        reinterpret_cast<const void *>(&k_cols_conv<2, true>),
+        reinterpret_cast<const void *>(&k_rows_r2c<SPLIT>),
+        reinterpret_cast<const void *>(&k_rows_c2r<SPLIT>),
+        reinterpret_cast<const void *>(&k_cols_conv<1, false, SPLIT>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, false, SPLIT>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, true, SPLIT>),
     };
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t set_kernel_attributes()
+{
+    hipError_t e = generic_attributes<0>();
+    if (e == hipSuccess) e = generic_attributes<1>();
+    if (e == hipSuccess) e = generic_attributes<2>();
+    return e;
 }
 
 }  // namespace lp

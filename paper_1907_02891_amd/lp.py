@@ -27,6 +27,7 @@ LP_OK, LP_E_INVALID, LP_E_SIZE, LP_E_STATE, LP_E_NOMEM, LP_E_DEVICE = 0, -1, -2,
 FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
 KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
 STAGE_ROWS, STAGE_COLUMNS = 0, 1
+PRECISION_FP32, PRECISION_SPLIT_FP16, PRECISION_SPLIT_BF16 = 0, 1, 2
 MAX_PY, MAX_PX = 20480, 40958
 
 _vp = ctypes.c_void_p
@@ -56,6 +57,8 @@ _SIGS = {
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
     "lp_plan_set_kernels": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_kernels": ([_vp], ctypes.c_int),
+    "lp_plan_set_precision": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_precision": ([_vp], ctypes.c_int),
     "lp_plan_variant_count": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_get_variant": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_set_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
@@ -129,7 +132,8 @@ class Plan:
             self.set_padding(*padding)
 
     def close(self):
-        if getattr(self, "_p", None):
+        # _lib is None when the interpreter tears the module down first
+        if getattr(self, "_p", None) and _lib is not None:
             _lib.lp_plan_destroy(self._p)
             self._p = None
 
@@ -226,6 +230,15 @@ class Plan:
     def kernels(self):
         return int(_lib.lp_plan_kernels(self._p))
 
+    def set_precision(self, mode):
+        """PRECISION_FP32, PRECISION_SPLIT_FP16 or PRECISION_SPLIT_BF16
+        (radix-16 passes on matrix cores); before bind."""
+        _check(_lib.lp_plan_set_precision(self._p, int(mode)))
+
+    @property
+    def precision(self):
+        return int(_lib.lp_plan_precision(self._p))
+
     def variant_count(self, stage):
         return int(_lib.lp_plan_variant_count(self._p, int(stage)))
 
@@ -281,7 +294,7 @@ class Batch:
         self.workspace = None
 
     def close(self):
-        if getattr(self, "_b", None):
+        if getattr(self, "_b", None) and _lib is not None:
             _lib.lp_batch_destroy(self._b)
             self._b = None
 
@@ -361,11 +374,13 @@ def spec_lengths():
     return tuple(out)
 
 
-def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO):
+def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO,
+              precision=PRECISION_FP32):
     """Plan + workspace + kernel spectrum in one call."""
     psf = np.asarray(psf)
     p = Plan(ny, nx, psf.shape[0], psf.shape[1], pitch_km, padding)
     p.set_kernels(kernels)
+    p.set_precision(precision)
     p.bind(device=device)
     p.set_kernel(psf)
     return p

@@ -164,3 +164,23 @@ def test_batch_contract_errors():
     assert lib.lp_convolve_batched(b._b, fake, fake) == lp.LP_E_NOMEM
     assert lib.lp_batch_set_variant(b._b, 0, 7, 0) == lp.LP_E_INVALID
     assert lib.lp_batch_set_variant(b._b, 0, lp.STAGE_ROWS, 99) == lp.LP_E_INVALID
+
+
+def test_precision_modes_host_side():
+    lib = lp.raw()
+    p = lp.Plan(16384, 16384, 2001, 2001)
+    assert p.precision == lp.PRECISION_FP32 and p.kernels == lp.KERNELS_SPECIALISED
+    ws = p.workspace_bytes
+    for mode in (lp.PRECISION_SPLIT_FP16, lp.PRECISION_SPLIT_BF16, lp.PRECISION_FP32):
+        p.set_precision(mode)
+        assert p.precision == mode
+        # the split forms run the generic kernels; the layout does not change
+        assert p.kernels == (lp.KERNELS_SPECIALISED if mode == lp.PRECISION_FP32 else lp.KERNELS_GENERIC)
+        assert p.workspace_bytes == ws
+    for bad in (-1, 3, 99):
+        with pytest.raises(lp.LPError) as ei:
+            p.set_precision(bad)
+        assert ei.value.code == lp.LP_E_INVALID
+    assert p.precision == lp.PRECISION_FP32
+    assert lib.lp_plan_precision(None) == -1
+    assert lib.lp_plan_set_precision(None, 1) == lp.LP_E_INVALID

@@ -177,6 +177,27 @@ def conv_same_separable_pixels(R, u, v, idx):
     return out
 
 
+def conv_same_classes(Rs, Ks):
+    """Several factorable source classes (Sec. 2.2, Eq. 4): class t has its
+    own radiance map R_t and kernel K_t (its angular-spectral pattern folded
+    into the kernel as in Eq. 6), and the sky brightness is the sum over
+    classes of the "same" convolutions K_t (*) R_t."""
+    assert len(Rs) == len(Ks) and len(Rs) >= 1
+    S = conv_same(Rs[0], Ks[0])
+    for R, K in zip(Rs[1:], Ks[1:]):
+        S += conv_same(R, K)
+    return S
+
+
+def conv_same_classes_pixels(Rs, Ks, idx):
+    """Class sum of Eq. 4 at flat pixel indices."""
+    assert len(Rs) == len(Ks) and len(Rs) >= 1
+    out = conv_same_pixels(Rs[0], Ks[0], idx)
+    for R, K in zip(Rs[1:], Ks[1:]):
+        out += conv_same_pixels(R, K, idx)
+    return out
+
+
 def rel_l2(x, ref):
     """||x - ref||_2 / ||ref||_2 in FP64."""
     x = np.asarray(x, np.float64).ravel()

@@ -353,3 +353,35 @@ def test_site_loss_gradient_by_central_differences():
         Rp[p] -= 2 * h
         Lm = loss(Rp.reshape(ny, nx))
         assert (Lp - Lm) / (2 * h) == pytest.approx(grad[p], rel=1e-9, abs=1e-11)
+
+
+# ------------------------------------------------- source classes (Eq. 4) --
+
+@pytest.mark.parametrize("shape", [(5, 7, 3, 3), (4, 9, 5, 6), (7, 7, 7, 7)])
+def test_class_sum_matches_brute_force(shape):
+    """Eq. 4: B = sum over classes of K_t (*) L_1t, against four Python loops
+    per class."""
+    rng = np.random.default_rng(11)
+    Rs, Ks = zip(*[rand_pair(rng, *shape, signed=True) for _ in range(3)])
+    got = oracle.conv_same_classes(Rs, Ks)
+    ref = sum(np.array(brute_same(R.tolist(), K.tolist())) for R, K in zip(Rs, Ks))
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_class_sum_with_one_kernel_is_conv_of_summed_maps():
+    """Classes sharing a kernel collapse to one class with the summed radiance
+    (Eq. 4 reduces to Eq. 3)."""
+    rng = np.random.default_rng(12)
+    K = rng.random((9, 7))
+    Rs = [rng.random((30, 41)) for _ in range(4)]
+    got = oracle.conv_same_classes(Rs, [K] * 4)
+    np.testing.assert_allclose(got, oracle.conv_same(sum(Rs), K), rtol=1e-12, atol=1e-12)
+
+
+def test_class_sum_pixels_match_full_field():
+    rng = np.random.default_rng(13)
+    Rs = [rng.random((25, 19)) for _ in range(3)]
+    Ks = [rng.random((5, 8)) for _ in range(3)]
+    full = oracle.conv_same_classes(Rs, Ks).ravel()
+    idx = rng.choice(full.size, 40, replace=False)
+    np.testing.assert_allclose(oracle.conv_same_classes_pixels(Rs, Ks, idx), full[idx], rtol=1e-13)

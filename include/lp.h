@@ -143,6 +143,40 @@ int lp_convolve(lp_plan *plan, const float *radiance, float *out);
  * ny*nx in and out (may alias).  Same errors as lp_convolve. */
 int lp_adjoint(lp_plan *plan, const float *grad_out, float *grad_in);
 
+/* ------------------------------------------------------ source classes --
+ * Sources grouped into T classes, each factorable with its own angular and
+ * spectral pattern (Sec. 2.2, Eq. 4): class t has its own radiance map L_1t
+ * and its own kernel K_t (Eq. 6 with L_2t), and the sky brightness is
+ * B = sum_t K_t (*) L_1t.  The products of Eq. 9 are summed in the Fourier
+ * domain, so the T maps share one inverse transform.
+ * lp_plan_set_classes: 1 <= T <= LP_MAX_CLASSES, before lp_plan_bind
+ * (LP_E_STATE after); the workspace then holds T intermediates and T
+ * spectra.  On a plan with T > 1, lp_kernel_spectrum, lp_convolve and
+ * lp_adjoint return LP_E_STATE.  lp_plan_classes: T (-1 for NULL). */
+#define LP_MAX_CLASSES 16
+int lp_plan_set_classes(lp_plan *plan, int n_classes);
+int lp_plan_classes(const lp_plan *plan);
+
+/* Spectra of the T kernels (host array of T host pointers, each FP64
+ * ky*kx row-major; read during the call only), computed as
+ * lp_kernel_spectrum does; one storage form for all: the real quadrant only
+ * if every kernel is mirror-symmetric.  Synchronises the bound stream.
+ * Errors as lp_kernel_spectrum. */
+int lp_kernel_spectra(lp_plan *plan, const double *const *psfs);
+
+/* B = sum_t K_t (*) L_1t cropped to ny x nx.  radiance: host array of T
+ * device pointers to FP32 ny*nx maps; out: device FP32 ny*nx (may alias any
+ * of them).  The rows forward stage runs once per class, the column stage
+ * transforms each class, multiplies by its spectrum and sums before one
+ * inverse transform, the rows inverse stage runs once.  Errors as
+ * lp_convolve. */
+int lp_convolve_classes(lp_plan *plan, const float *const *radiance, float *out);
+
+/* Gradient with respect to class cls's map: grad_in = C_cls^T grad_out
+ * (lp_adjoint with kernel cls).  Device FP32 ny*nx in and out (may alias).
+ * LP_E_INVALID for cls outside [0, T). */
+int lp_adjoint_class(lp_plan *plan, int cls, const float *grad_out, float *grad_in);
+
 /* Per-stage timing with HIP events on the bound stream.  enable != 0 starts
  * recording events around each of the three stages of every lp_convolve /
  * lp_adjoint call (up to 1024 calls are kept); lp_plan_stage_ms synchronises

@@ -213,6 +213,8 @@ struct lp_plan {
     size_t twc_max = 2, twr_max = 2;       // table floats reserved (largest variant)
     int variant = 0;  // 0: specialised kernels where available, 1: generic only
     int precision = LP_PRECISION_FP32;  // split forms run the generic kernels
+    int classes = 1;                    // source classes summed (Eq. 4)
+    size_t w_class = 0, kh_class = 0;   // bytes per class of intermediate / spectrum
     std::vector<float> twc;  // its four pass tables, concatenated
     size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
     // register-resident row stages (if the half row length has one)
@@ -245,9 +247,11 @@ void layout(lp_plan *p)
     const size_t scratch = align256(p->ky * p->kx * 8) + align256(p->ky * p->h * 16) +
                            align256(p->px * 16) + align256(p->py * 16);
     p->scratch_bytes = scratch;
+    p->w_class = align256(w);
+    p->kh_class = align256(static_cast<size_t>(p->nblk) * p->py * C * 8);
     p->off_w = 0;
-    p->off_kh = align256(std::max(w, scratch));
-    p->off_twx = p->off_kh + align256(static_cast<size_t>(p->nblk) * p->py * C * 8);
+    p->off_kh = align256(std::max(p->w_class * p->classes, scratch));
+    p->off_twx = p->off_kh + p->kh_class * p->classes;
     p->off_rtw = p->off_twx + align256(p->twx.size() * 4);
     p->off_twy = p->off_rtw + align256(p->rtw.size() * 4);
     p->off_twc = p->off_twy + align256(p->twy.size() * 4);
@@ -381,24 +385,34 @@ lp::ColArgs col_args(const lp_plan *p)
     a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twy);
     a.kh = p->ws + p->off_kh;
     a.mf = p->ws + p->off_mf;
+    a.classes = p->classes;
+    a.w_stride = static_cast<int64_t>(p->w_class / 8);
+    a.kh_stride = static_cast<int64_t>(p->kh_class);
     return a;
 }
 
 bool attributes_set = false;
 
-int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *who)
+// The three stages.  ins: nin maps (nin = the plan's classes for a class
+// sum, else 1); kh_class: the class whose spectrum a single-map call uses.
+int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjoint, int kh_class,
+             const char *who)
 {
     if (!p) return fail(LP_E_INVALID, "%s: null plan", who);
-    if (!in || !out) return fail(LP_E_INVALID, "%s: null data pointer", who);
+    if (!ins || !out) return fail(LP_E_INVALID, "%s: null data pointer", who);
+    for (int t = 0; t < nin; ++t)
+        if (!ins[t]) return fail(LP_E_INVALID, "%s: null data pointer", who);
     if (!p->bound) return fail(LP_E_NOMEM, "%s: no workspace bound", who);
     if (p->form == LP_FORM_NONE) return fail(LP_E_STATE, "%s: kernel spectrum not computed", who);
+    const bool sum = nin > 1;
     hipError_t e;
     const bool rec = p->timing && p->ev_calls < kMaxTimedCalls;
     hipEvent_t *ev = rec ? &p->ev[4 * p->ev_calls] : nullptr;
     if (rec && (e = hipEventRecord(ev[0], p->stream)) != hipSuccess) return fail_hip(e, who);
     float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
     const lp::RowArgs ra = row_args(p);
-    const lp::ColArgs ca = col_args(p);
+    lp::ColArgs ca = col_args(p);
+    ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
     const bool spec_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
     const bool rspec = p->row_spec >= 0 && spec_ok;
     lp::RowRegArgs rr{};
@@ -411,11 +425,13 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
         rr.tw_f2 = twr + p->twr_off[1];
         rr.tw_i1 = twr + p->twr_off[2];
         rr.tw_i2 = twr + p->twr_off[3];
-        e = lp::launch_rows_r2c_reg(in, W, rr, p->row_spec, p->stream);
-    } else {
-        e = lp::launch_rows_r2c(in, W, ra, p->t_rows, p->stream);
     }
-    if (e != hipSuccess) return fail_hip(e, "rows forward launch");
+    for (int t = 0; t < nin; ++t) {
+        float2 *Wt = reinterpret_cast<float2 *>(p->ws + p->off_w + static_cast<size_t>(t) * p->w_class);
+        e = rspec ? lp::launch_rows_r2c_reg(ins[t], Wt, rr, p->row_spec, p->stream)
+                  : lp::launch_rows_r2c(ins[t], Wt, ra, p->t_rows, p->stream);
+        if (e != hipSuccess) return fail_hip(e, "rows forward launch");
+    }
     if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
     if (p->col_spec >= 0 && spec_ok) {
         lp::ColRegArgs cr{};
@@ -423,15 +439,20 @@ int run_path(lp_plan *p, const float *in, float *out, bool adjoint, const char *
         cr.ny = static_cast<int32_t>(p->ny);
         cr.ku = ca.ku;
         cr.kh = ca.kh;
+        cr.classes = nin;
+        cr.w_stride = ca.w_stride;
+        cr.kh_stride = ca.kh_stride;
         cr.tw_f1 = twc + p->twc_off[0];
         cr.tw_f2 = twc + p->twc_off[1];
         cr.tw_i1 = twc + p->twc_off[2];
         cr.tw_i2 = twc + p->twc_off[3];
         if ((e = lp::launch_cols_reg(W, cr, p->col_spec, static_cast<int>(p->h), p->form, adjoint,
-                                     p->stream)) != hipSuccess)
+                                     p->stream, nullptr, 1, sum)) != hipSuccess)
             return fail_hip(e, "column stage launch");
-    } else if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream)) != hipSuccess) {
-        return fail_hip(e, "column stage launch");
+    } else {
+        ca.classes = nin;
+        if ((e = lp::launch_cols_conv(W, ca, p->form, adjoint, p->t_cols, p->stream, sum)) != hipSuccess)
+            return fail_hip(e, "column stage launch");
     }
     if (rec && (e = hipEventRecord(ev[2], p->stream)) != hipSuccess) return fail_hip(e, who);
     e = rspec ? lp::launch_rows_c2r_reg(W, out, rr, p->row_spec, p->stream)
@@ -641,22 +662,30 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
     return LP_OK;
 }
 
-int lp_kernel_spectrum(lp_plan *p, const double *psf)
+namespace {
+
+// Spectra of n kernels (classes 0 .. n-1), one storage form for all: the
+// real quadrant only if every kernel is exactly mirror-symmetric on both
+// axes with odd sizes (then its spectrum is real and even).
+int kernel_spectra(lp_plan *p, const double *const *psfs, int n, const char *who)
 {
-    clear_error();
-    if (!p) return fail(LP_E_INVALID, "null plan");
-    if (!psf) return fail(LP_E_INVALID, "null kernel");
     const int64_t ky = p->ky, kx = p->kx;
-    for (int64_t i = 0; i < ky * kx; ++i)
-        if (!std::isfinite(psf[i])) return fail(LP_E_INVALID, "kernel entry %lld is not finite", (long long)i);
-    if (!p->bound) return fail(LP_E_STATE, "lp_kernel_spectrum before lp_plan_bind");
-    // Exact mirror symmetry on both axes (odd sizes) => real, even spectrum.
+    for (int t = 0; t < n; ++t) {
+        if (!psfs[t]) return fail(LP_E_INVALID, "%s: null kernel", who);
+        for (int64_t i = 0; i < ky * kx; ++i)
+            if (!std::isfinite(psfs[t][i]))
+                return fail(LP_E_INVALID, "%s: kernel %d entry %lld is not finite", who, t, (long long)i);
+    }
+    if (!p->bound) return fail(LP_E_STATE, "%s before lp_plan_bind", who);
     bool sym = (ky % 2 == 1) && (kx % 2 == 1);
-    for (int64_t a = 0; sym && a < ky; ++a)
-        for (int64_t b = 0; b < kx; ++b) {
-            const double v = psf[a * kx + b];
-            if (v != psf[(ky - 1 - a) * kx + b] || v != psf[a * kx + (kx - 1 - b)]) { sym = false; break; }
-        }
+    for (int t = 0; sym && t < n; ++t) {
+        const double *psf = psfs[t];
+        for (int64_t a = 0; sym && a < ky; ++a)
+            for (int64_t b = 0; b < kx; ++b) {
+                const double v = psf[a * kx + b];
+                if (v != psf[(ky - 1 - a) * kx + b] || v != psf[a * kx + (kx - 1 - b)]) { sym = false; break; }
+            }
+    }
     const int form = sym ? LP_FORM_REAL_QUADRANT : LP_FORM_COMPLEX;
     // FP64 twiddle tables exp(-2 pi i m / N)
     std::vector<double> tabx(2 * p->px), taby(2 * p->py);
@@ -672,31 +701,60 @@ int lp_kernel_spectrum(lp_plan *p, const double *psf)
         taby[2 * m] = c;
         taby[2 * m + 1] = -s;
     }
-    // scratch (overlaps the intermediate, unused until lp_convolve)
+    // scratch (overlaps the intermediate, unused until the next convolution)
     char *sc = p->ws + p->off_w;
     double *dK = reinterpret_cast<double *>(sc);
     double2 *dT1 = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8));
     double2 *dTabx = reinterpret_cast<double2 *>(sc + align256(ky * kx * 8) + align256(ky * p->h * 16));
     double2 *dTaby = reinterpret_cast<double2 *>(reinterpret_cast<char *>(dTabx) + align256(p->px * 16));
     hipError_t e;
-    if ((e = hipMemcpyAsync(dK, psf, ky * kx * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(dTabx, tabx.data(), tabx.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
+    p->form = LP_FORM_NONE;
+    if ((e = hipMemcpyAsync(dTabx, tabx.data(), tabx.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(dTaby, taby.data(), taby.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return fail_hip(e, "kernel upload");
     const int cy = static_cast<int>((ky - 1) / 2), cx = static_cast<int>((kx - 1) / 2);
-    if ((e = lp::launch_spec_rows(dK, static_cast<int>(ky), static_cast<int>(kx), cx,
-                                  static_cast<int>(p->px), static_cast<int>(p->h), dTabx, dT1,
-                                  p->stream)) != hipSuccess)
-        return fail_hip(e, "spectrum rows launch");
     const int ku = static_cast<int>(sym ? p->py / 2 + 1 : p->py);
     const double scale = 1.0 / (static_cast<double>(p->py) * static_cast<double>(p->px));
-    if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), cy, static_cast<int>(p->py), ku,
-                                  static_cast<int>(p->h), p->logc, static_cast<int>(p->nblk), dTaby,
-                                  scale, form, p->ws + p->off_kh, p->stream)) != hipSuccess)
-        return fail_hip(e, "spectrum columns launch");
-    if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "kernel spectrum");
+    for (int t = 0; t < n; ++t) {
+        // one kernel at a time through the scratch: the copy of kernel t+1
+        // is ordered after kernel t's spectrum kernels on the stream
+        if ((e = hipMemcpyAsync(dK, psfs[t], ky * kx * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess)
+            return fail_hip(e, "kernel upload");
+        if ((e = lp::launch_spec_rows(dK, static_cast<int>(ky), static_cast<int>(kx), cx,
+                                      static_cast<int>(p->px), static_cast<int>(p->h), dTabx, dT1,
+                                      p->stream)) != hipSuccess)
+            return fail_hip(e, "spectrum rows launch");
+        if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), cy, static_cast<int>(p->py), ku,
+                                      static_cast<int>(p->h), p->logc, static_cast<int>(p->nblk), dTaby,
+                                      scale, form, p->ws + p->off_kh + static_cast<size_t>(t) * p->kh_class,
+                                      p->stream)) != hipSuccess)
+            return fail_hip(e, "spectrum columns launch");
+        // pageable host source: the copy may return before the transfer is
+        // done, so wait before the next kernel overwrites dK
+        if ((e = hipStreamSynchronize(p->stream)) != hipSuccess) return fail_hip(e, "kernel spectrum");
+    }
     p->form = form;
     return LP_OK;
+}
+
+}  // namespace
+
+int lp_kernel_spectrum(lp_plan *p, const double *psf)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (!psf) return fail(LP_E_INVALID, "null kernel");
+    if (p->classes != 1)
+        return fail(LP_E_STATE, "lp_kernel_spectrum on a plan of %d classes: use lp_kernel_spectra", p->classes);
+    return kernel_spectra(p, &psf, 1, "lp_kernel_spectrum");
+}
+
+int lp_kernel_spectra(lp_plan *p, const double *const *psfs)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (!psfs) return fail(LP_E_INVALID, "null kernel array");
+    return kernel_spectra(p, psfs, p->classes, "lp_kernel_spectra");
 }
 
 int lp_plan_spectrum_form(const lp_plan *p) { return p ? p->form : LP_FORM_NONE; }
@@ -738,14 +796,48 @@ int lp_plan_read_spectrum(lp_plan *p, float *out)
 int lp_convolve(lp_plan *p, const float *radiance, float *out)
 {
     clear_error();
-    return run_path(p, radiance, out, false, "lp_convolve");
+    if (p && p->classes != 1)
+        return fail(LP_E_STATE, "lp_convolve on a plan of %d classes: use lp_convolve_classes", p->classes);
+    return run_path(p, &radiance, 1, out, false, 0, "lp_convolve");
 }
 
 int lp_adjoint(lp_plan *p, const float *grad_out, float *grad_in)
 {
     clear_error();
-    return run_path(p, grad_out, grad_in, true, "lp_adjoint");
+    if (p && p->classes != 1)
+        return fail(LP_E_STATE, "lp_adjoint on a plan of %d classes: use lp_adjoint_class", p->classes);
+    return run_path(p, &grad_out, 1, grad_in, true, 0, "lp_adjoint");
 }
+
+int lp_convolve_classes(lp_plan *p, const float *const *radiance, float *out)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (!radiance) return fail(LP_E_INVALID, "lp_convolve_classes: null map array");
+    return run_path(p, radiance, p->classes, out, false, 0, "lp_convolve_classes");
+}
+
+int lp_adjoint_class(lp_plan *p, int cls, const float *grad_out, float *grad_in)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (cls < 0 || cls >= p->classes)
+        return fail(LP_E_INVALID, "class %d outside [0, %d)", cls, p->classes);
+    return run_path(p, &grad_out, 1, grad_in, true, cls, "lp_adjoint_class");
+}
+
+int lp_plan_set_classes(lp_plan *p, int n)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    if (n < 1 || n > LP_MAX_CLASSES) return fail(LP_E_INVALID, "classes %d outside [1, %d]", n, LP_MAX_CLASSES);
+    if (p->bound) return fail(LP_E_STATE, "classes must be set before lp_plan_bind");
+    p->classes = n;
+    layout(p);
+    return LP_OK;
+}
+
+int lp_plan_classes(const lp_plan *p) { return p ? p->classes : -1; }
 
 int lp_plan_timing(lp_plan *p, int enable)
 {

@@ -59,6 +59,9 @@ struct ColArgs {
     const float2 *tw;
     const void *kh;     // blocked spectrum (float2 complex or float real)
     const void *mf;     // matrix-core fragment table (split precision only)
+    int32_t classes;    // source classes summed before the inverse (class-sum kernels)
+    int64_t w_stride;   // float2 elements from one class's intermediate to the next
+    int64_t kh_stride;  // bytes from one class's spectrum to the next
 };
 
 // Bytes of the fragment table of the split-precision radix-16 passes (both
@@ -70,7 +73,7 @@ hipError_t launch_mfma_fragments(int split, void *table, hipStream_t s);
 hipError_t launch_rows_r2c(const float *R, float2 *W, const RowArgs &a, int threads,
                            hipStream_t s);
 hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, int threads,
-                            hipStream_t s);
+                            hipStream_t s, bool class_sum = false);
 hipError_t launch_rows_c2r(const float2 *W, float *S, const RowArgs &a, int threads,
                            hipStream_t s);
 hipError_t launch_spec_rows(const double *K, int ky, int kx, int cx, int px, int h,
@@ -115,6 +118,9 @@ struct ColRegArgs {
     int32_t ny;          // stored rows per column
     int32_t ku;          // stored spectrum rows per column (n or n/2+1)
     const void *kh;      // column-major spectrum (float real quadrant or float2)
+    int32_t classes;     // source classes summed before the inverse (class-sum kernels)
+    int64_t w_stride;    // float2 elements from one class's intermediate to the next
+    int64_t kh_stride;   // bytes from one class's spectrum to the next
     const float2 *tw_f1; // exp(-2 pi i j k / (R0 R1)),      k < R0,      1 <= j < R1
     const float2 *tw_f2; // exp(-2 pi i j k / N),            k < R0 R1,   1 <= j < R2
     const float2 *tw_i1; // exp(-2 pi i j k / (R2 R1)),      k < R2,      1 <= j < R1
@@ -136,7 +142,8 @@ struct BatchItem {
 int col_spec_index(int n, int k = 0);
 int col_spec_count(int n);
 hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
-                           hipStream_t s, const BatchItem *items = nullptr, int nitems = 1);
+                           hipStream_t s, const BatchItem *items = nullptr, int nitems = 1,
+                           bool class_sum = false);
 
 }  // namespace lp
 

@@ -79,8 +79,11 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
 // ---------------------------------------------------------------- columns
 // FORM 1: real even spectrum, one quadrant stored, (py/2+1) rows per block.
 // FORM 2: complex spectrum, py rows per block.  CONJ: use conj(Khat) (the
-// transposed operator).
-template <int FORM, bool CONJ, int SPLIT>
+// transposed operator).  ACC > 0: several source classes (Eq. 4); class t's
+// block sits a.w_stride elements after class 0's and its spectrum
+// a.kh_stride bytes after class 0's; the products are summed in registers
+// (at most ACC per thread) before the one inverse transform.
+template <int FORM, bool CONJ, int SPLIT, int ACC>
 __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColArgs a)
 {
     extern __shared__ float2 lds[];
@@ -92,22 +95,50 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
     const int stored = a.ny << a.logc;
     float2 *blk = W + static_cast<int64_t>(vb) * stored;
 
-    for (int e = tid; e < total; e += nt)
-        lds[e] = (e < stored) ? blk[e] : make_float2(0.f, 0.f);
-    __syncthreads();
-    lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
-
-    if constexpr (FORM == 1) {
-        const float *kq = static_cast<const float *>(a.kh) + static_cast<int64_t>(vb) * (a.ku << a.logc);
-        for (int e = tid; e < total; e += nt) {
+    // spectrum value of element e of this block for one class
+    auto spec = [&](const void *kh, int e, float2 x) {
+        if constexpr (FORM == 1) {
+            const float *kq = static_cast<const float *>(kh) + static_cast<int64_t>(vb) * (a.ku << a.logc);
             const int u = e >> a.logc, c = e & (C - 1);
             const int uq = (2 * u <= py) ? u : py - u;
-            lds[e] = cscale(lds[e], kq[(uq << a.logc) + c]);
+            return cscale(x, kq[(uq << a.logc) + c]);
+        } else {
+            const float2 k = (static_cast<const float2 *>(kh) + static_cast<int64_t>(vb) * total)[e];
+            return CONJ ? cmulc(x, k) : cmul(x, k);
+        }
+    };
+
+    if constexpr (ACC > 0) {
+        float2 acc[ACC];
+#pragma unroll
+        for (int q = 0; q < ACC; ++q) acc[q] = make_float2(0.f, 0.f);
+        for (int t = 0; t < a.classes; ++t) {
+            const float2 *src = blk + t * a.w_stride;
+            const void *kh = static_cast<const char *>(a.kh) + t * a.kh_stride;
+            __syncthreads();  // the previous class's products are all read
+            for (int e = tid; e < total; e += nt)
+                lds[e] = (e < stored) ? src[e] : make_float2(0.f, 0.f);
+            __syncthreads();
+            lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, opaque_v(tid), nt, a.mf);
+            const int t0 = opaque_v(tid);
+#pragma unroll
+            for (int q = 0; q < ACC; ++q) {
+                const int e = t0 + q * nt;
+                if (e < total) acc[q] = cadd(acc[q], spec(kh, e, lds[e]));
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ACC; ++q) {
+            const int e = tid + q * nt;
+            if (e < total) lds[e] = acc[q];
         }
     } else {
-        const float2 *kc = static_cast<const float2 *>(a.kh) + static_cast<int64_t>(vb) * total;
         for (int e = tid; e < total; e += nt)
-            lds[e] = CONJ ? cmulc(lds[e], kc[e]) : cmul(lds[e], kc[e]);
+            lds[e] = (e < stored) ? blk[e] : make_float2(0.f, 0.f);
+        __syncthreads();
+        lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
+        for (int e = tid; e < total; e += nt) lds[e] = spec(a.kh, e, lds[e]);
     }
     __syncthreads();
     lds_fft<true, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
@@ -297,27 +328,43 @@ hipError_t launch_rows_c2r(const float2 *W, float *S, const RowArgs &a, int thre
     return hipGetLastError();
 }
 
-template <int SPLIT>
-static void launch_cols_split(float2 *W, const ColArgs &a, int form, bool conj_k, dim3 g, dim3 t,
-                              size_t lds, hipStream_t s)
+template <int SPLIT, int ACC>
+static void launch_cols_sum(float2 *W, const ColArgs &a, int form, dim3 g, dim3 t, size_t lds, hipStream_t s)
 {
     if (form == 1)
-        hipLaunchKernelGGL((k_cols_conv<1, false, SPLIT>), g, t, lds, s, W, a);
-    else if (conj_k)
-        hipLaunchKernelGGL((k_cols_conv<2, true, SPLIT>), g, t, lds, s, W, a);
+        hipLaunchKernelGGL((k_cols_conv<1, false, SPLIT, ACC>), g, t, lds, s, W, a);
     else
-        hipLaunchKernelGGL((k_cols_conv<2, false, SPLIT>), g, t, lds, s, W, a);
+        hipLaunchKernelGGL((k_cols_conv<2, false, SPLIT, ACC>), g, t, lds, s, W, a);
+}
+
+template <int SPLIT>
+static void launch_cols_split(float2 *W, const ColArgs &a, int form, bool conj_k, bool sum, dim3 g,
+                              dim3 t, size_t lds, hipStream_t s)
+{
+    // class sums: 8 accumulators per thread when they suffice, else kEltsPerThread
+    if (sum && (a.py << a.logc) <= 8 * static_cast<int>(t.x))
+        launch_cols_sum<SPLIT, 8>(W, a, form, g, t, lds, s);
+    else if (sum)
+        launch_cols_sum<SPLIT, kEltsPerThread>(W, a, form, g, t, lds, s);
+    else if (form == 1)
+        hipLaunchKernelGGL((k_cols_conv<1, false, SPLIT, 0>), g, t, lds, s, W, a);
+    else if (conj_k)
+        hipLaunchKernelGGL((k_cols_conv<2, true, SPLIT, 0>), g, t, lds, s, W, a);
+    else
+        hipLaunchKernelGGL((k_cols_conv<2, false, SPLIT, 0>), g, t, lds, s, W, a);
 }
 
 hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, int threads,
-                            hipStream_t s)
+                            hipStream_t s, bool class_sum)
 {
+    if (class_sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
+    if (threads * kEltsPerThread < (a.py << a.logc)) return hipErrorInvalidValue;
     const size_t lds = static_cast<size_t>(a.py) << a.logc << 3;
     const dim3 g(a.nblk), t(threads);
     switch (a.fy.split) {
-        case 1: launch_cols_split<1>(W, a, form, conj_k, g, t, lds, s); break;
-        case 2: launch_cols_split<2>(W, a, form, conj_k, g, t, lds, s); break;
-        default: launch_cols_split<0>(W, a, form, conj_k, g, t, lds, s); break;
+        case 1: launch_cols_split<1>(W, a, form, conj_k, class_sum, g, t, lds, s); break;
+        case 2: launch_cols_split<2>(W, a, form, conj_k, class_sum, g, t, lds, s); break;
+        default: launch_cols_split<0>(W, a, form, conj_k, class_sum, g, t, lds, s); break;
     }
     return hipGetLastError();
 }
@@ -347,9 +394,13 @@ static hipError_t generic_attributes()
     const void *fns[] = {
         reinterpret_cast<const void *>(&k_rows_r2c<SPLIT>),
         reinterpret_cast<const void *>(&k_rows_c2r<SPLIT>),
-        reinterpret_cast<const void *>(&k_cols_conv<1, false, SPLIT>),
-        reinterpret_cast<const void *>(&k_cols_conv<2, false, SPLIT>),
-        reinterpret_cast<const void *>(&k_cols_conv<2, true, SPLIT>),
+        reinterpret_cast<const void *>(&k_cols_conv<1, false, SPLIT, 0>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, false, SPLIT, 0>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, true, SPLIT, 0>),
+        reinterpret_cast<const void *>(&k_cols_conv<1, false, SPLIT, 8>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, false, SPLIT, 8>),
+        reinterpret_cast<const void *>(&k_cols_conv<1, false, SPLIT, kEltsPerThread>),
+        reinterpret_cast<const void *>(&k_cols_conv<2, false, SPLIT, kEltsPerThread>),
     };
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
@@ -378,8 +429,12 @@ namespace lp {
 // pass consumes the forward's last-pass outputs straight from registers), and
 // only rows < ny read or written.  Column-major intermediate: column v is the
 // contiguous run W[v * ny .. v * ny + ny).
-template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ>
-__global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a,
+// SUM (several source classes, Eq. 4): the forward transform and the product
+// with the class's spectrum are repeated for each class t (intermediate
+// W + t w_stride, spectrum kh + t kh_stride bytes) and summed in registers
+// before the one inverse transform, whose result goes to class 0's column.
+template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ, bool SUM>
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a,
                                                                          const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
@@ -401,61 +456,80 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_cols_reg(float2 
     }
     float2 *col = W + static_cast<int64_t>(v) * ny;
 
-    float2 x0[F0::S][R0];
-    if (act) {
+    // forward transform of one column and product with one spectrum, left in
+    // x2 in the order the inverse's first pass takes it
+    auto forward = [&](const float2 *__restrict__ src, const void *kh, float2 (&x2)[F2::S][R2]) {
+        float2 x0[F0::S][R0];
+        if (act) {
 #pragma unroll
-        for (int s = 0; s < F0::S; ++s) {
-            const int i = tt + s * TF;
-            if (F0::NB % TF == 0 || i < F0::NB) {
+            for (int s = 0; s < F0::S; ++s) {
+                const int i = tt + s * TF;
+                if (F0::NB % TF == 0 || i < F0::NB) {
 #pragma unroll
-                for (int j = 0; j < R0; ++j) {
-                    const int n = i + j * F0::NB;
-                    x0[s][j] = (n < ny) ? col[n] : make_float2(0.f, 0.f);
+                    for (int j = 0; j < R0; ++j) {
+                        const int n = i + j * F0::NB;
+                        x0[s][j] = (n < ny) ? src[n] : make_float2(0.f, 0.f);
+                    }
+                }
+            }
+            F0::template butterfly<false>(x0, tt);
+            F0::store(x0, lds, tt, 0);
+        }
+        __syncthreads();
+        float2 x1[F1::S][R1];
+        if (act) {
+            F1::load(x1, lds, tt, 0);
+            F1::template twiddle<false>(x1, a.tw_f1, tt);
+            F1::template butterfly<false>(x1, tt);
+        }
+        __syncthreads();
+        if (act) F1::store(x1, lds, tt, 0);
+        __syncthreads();
+        if (act) {
+            F2::load(x2, lds, tt, 0);
+            F2::template twiddle<false>(x2, a.tw_f2, tt);
+            F2::template butterfly<false>(x2, tt);
+            // Eq. 9: pixel-wise product with the kernel spectrum, element u = i + j NB
+#pragma unroll
+            for (int s = 0; s < F2::S; ++s) {
+                const int i = tt + s * TF;
+                if (F2::NB % TF == 0 || i < F2::NB) {
+                    if constexpr (FORM == 1) {
+                        const float *kq = static_cast<const float *>(kh) + static_cast<int64_t>(v) * a.ku;
+#pragma unroll
+                        for (int j = 0; j < R2; ++j) {
+                            const int u = i + j * F2::NB;
+                            x2[s][j] = cscale(x2[s][j], kq[(2 * u <= N) ? u : N - u]);
+                        }
+                    } else {
+                        const float2 *kc = static_cast<const float2 *>(kh) + static_cast<int64_t>(v) * N;
+#pragma unroll
+                        for (int j = 0; j < R2; ++j) {
+                            const float2 k = kc[i + j * F2::NB];
+                            x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
+                        }
+                    }
                 }
             }
         }
-        F0::template butterfly<false>(x0, tt);
-        F0::store(x0, lds, tt, 0);
-    }
-    __syncthreads();
-    float2 x1[F1::S][R1];
-    if (act) {
-        F1::load(x1, lds, tt, 0);
-        F1::template twiddle<false>(x1, a.tw_f1, tt);
-        F1::template butterfly<false>(x1, tt);
-    }
-    __syncthreads();
-    if (act) F1::store(x1, lds, tt, 0);
-    __syncthreads();
+    };
+
     float2 x2[F2::S][R2];
-    if (act) {
-        F2::load(x2, lds, tt, 0);
-        F2::template twiddle<false>(x2, a.tw_f2, tt);
-        F2::template butterfly<false>(x2, tt);
-        // Eq. 9: pixel-wise product with the kernel spectrum, element u = i + j NB
+    forward(col, a.kh, x2);
+    if constexpr (SUM) {
+        for (int t = 1; t < a.classes; ++t) {
+            float2 z[F2::S][R2];
+            __syncthreads();  // every thread is done reading the exchange buffer
+            forward(col + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
+            if (act) {
 #pragma unroll
-        for (int s = 0; s < F2::S; ++s) {
-            const int i = tt + s * TF;
-            if (F2::NB % TF == 0 || i < F2::NB) {
-                if constexpr (FORM == 1) {
-                    const float *kq = static_cast<const float *>(a.kh) + static_cast<int64_t>(v) * a.ku;
+                for (int s = 0; s < F2::S; ++s)
 #pragma unroll
-                    for (int j = 0; j < R2; ++j) {
-                        const int u = i + j * F2::NB;
-                        x2[s][j] = cscale(x2[s][j], kq[(2 * u <= N) ? u : N - u]);
-                    }
-                } else {
-                    const float2 *kc = static_cast<const float2 *>(a.kh) + static_cast<int64_t>(v) * N;
-#pragma unroll
-                    for (int j = 0; j < R2; ++j) {
-                        const float2 k = kc[i + j * F2::NB];
-                        x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
-                    }
-                }
+                    for (int j = 0; j < R2; ++j) x2[s][j] = cadd(x2[s][j], z[s][j]);
             }
         }
-        I0::template butterfly<true>(x2, tt);
     }
+    if (act) I0::template butterfly<true>(x2, tt);
     __syncthreads();
     if (act) I0::store(x2, lds, tt, 0);
     __syncthreads();
@@ -514,11 +588,11 @@ static constexpr size_t col_lds_bytes()
     return static_cast<size_t>(xchg_words(kColSpecs[I].n, kColSpecs[I].r0, kColSpecs[I].r2)) * 8;
 }
 
-template <int I, int FORM, bool CONJ>
+template <int I, int FORM, bool CONJ, bool SUM = false>
 static const void *col_fn()
 {
     constexpr ColSpec c = kColSpecs[I];
-    return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ>);
+    return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
 }
 
 template <int I>
@@ -527,7 +601,8 @@ static hipError_t col_attrs_from()
     if constexpr (I >= kNumColSpecs) {
         return hipSuccess;
     } else {
-        const void *fns[] = {col_fn<I, 1, false>(), col_fn<I, 2, false>(), col_fn<I, 2, true>()};
+        const void *fns[] = {col_fn<I, 1, false>(), col_fn<I, 2, false>(), col_fn<I, 2, true>(),
+                             col_fn<I, 1, false, true>(), col_fn<I, 2, false, true>()};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
             if (e != hipSuccess) return e;
@@ -538,31 +613,37 @@ static hipError_t col_attrs_from()
 
 template <int I>
 static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int ncols, int form,
-                                  bool conj_k, hipStream_t s, const BatchItem *items, int nitems)
+                                  bool conj_k, hipStream_t s, const BatchItem *items, int nitems,
+                                  bool sum)
 {
     if constexpr (I >= kNumColSpecs) {
         return hipErrorInvalidValue;
     } else {
-        if (idx != I) return launch_col_from<I + 1>(idx, W, a, ncols, form, conj_k, s, items, nitems);
+        if (idx != I) return launch_col_from<I + 1>(idx, W, a, ncols, form, conj_k, s, items, nitems, sum);
         constexpr ColSpec c = kColSpecs[I];
         const dim3 g(ncols, nitems), t(((c.tf + 63) / 64) * 64);
         const size_t lds = col_lds_bytes<I>();
-        if (form == 1)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false>), g, t, lds, s, W, a, items);
+        if (sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
+        if (sum && form == 1)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false, true>), g, t, lds, s, W, a, items);
+        else if (sum)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false, true>), g, t, lds, s, W, a, items);
+        else if (form == 1)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false, false>), g, t, lds, s, W, a, items);
         else if (conj_k)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true>), g, t, lds, s, W, a, items);
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true, false>), g, t, lds, s, W, a, items);
         else
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false>), g, t, lds, s, W, a, items);
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false, false>), g, t, lds, s, W, a, items);
         return hipGetLastError();
     }
 }
 
 hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
-                           hipStream_t s, const BatchItem *items, int nitems)
+                           hipStream_t s, const BatchItem *items, int nitems, bool class_sum)
 {
     hipError_t e = set_spec_attributes();
     if (e != hipSuccess) return e;
-    return launch_col_from<0>(idx, W, a, ncols, form, conj_k, s, items, nitems);
+    return launch_col_from<0>(idx, W, a, ncols, form, conj_k, s, items, nitems, class_sum);
 }
 
 }  // namespace lp

@@ -28,6 +28,7 @@ FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
 KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
 STAGE_ROWS, STAGE_COLUMNS = 0, 1
 PRECISION_FP32, PRECISION_SPLIT_FP16, PRECISION_SPLIT_BF16 = 0, 1, 2
+MAX_CLASSES = 16
 MAX_PY, MAX_PX = 20480, 40958
 
 _vp = ctypes.c_void_p
@@ -58,6 +59,11 @@ _SIGS = {
     "lp_plan_set_kernels": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_kernels": ([_vp], ctypes.c_int),
     "lp_plan_set_precision": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_set_classes": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_classes": ([_vp], ctypes.c_int),
+    "lp_kernel_spectra": ([_vp, ctypes.POINTER(_dp)], ctypes.c_int),
+    "lp_convolve_classes": ([_vp, ctypes.POINTER(_vp), _vp], ctypes.c_int),
+    "lp_adjoint_class": ([_vp, ctypes.c_int, _vp, _vp], ctypes.c_int),
     "lp_plan_precision": ([_vp], ctypes.c_int),
     "lp_plan_variant_count": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_get_variant": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -184,6 +190,26 @@ class Plan:
         _check(_lib.lp_kernel_spectrum(self._p, psf.ctypes.data_as(_dp)))
         return self
 
+    def set_classes(self, n):
+        """Number of source classes summed by convolve_classes (before bind)."""
+        _check(_lib.lp_plan_set_classes(self._p, int(n)))
+
+    @property
+    def classes(self):
+        return int(_lib.lp_plan_classes(self._p))
+
+    def set_kernels_classes(self, psfs):
+        """One kernel per class (lp_kernel_spectra)."""
+        arrs = [np.ascontiguousarray(k, dtype=np.float64) for k in psfs]
+        if len(arrs) != self.classes:
+            raise ValueError(f"{len(arrs)} kernels for {self.classes} classes")
+        for k in arrs:
+            if k.shape != (self.ky, self.kx):
+                raise ValueError(f"kernel shape {k.shape} != ({self.ky}, {self.kx})")
+        ptrs = (_dp * len(arrs))(*[k.ctypes.data_as(_dp) for k in arrs])
+        _check(_lib.lp_kernel_spectra(self._p, ptrs))
+        return self
+
     @property
     def form(self):
         return int(_lib.lp_plan_spectrum_form(self._p))
@@ -219,6 +245,24 @@ class Plan:
         out = self._io(grad_out, out)
         _check(_lib.lp_adjoint(self._p, ctypes.c_void_p(grad_out.data_ptr()),
                                ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def convolve_classes(self, maps, out=None):
+        """B = sum_t K_t (*) L_t over the plan's classes (lp_convolve_classes)."""
+        if len(maps) != self.classes:
+            raise ValueError(f"{len(maps)} maps for {self.classes} classes")
+        out = self._io(maps[0], out)
+        for m in maps[1:]:
+            self._io(m, out)
+        ptrs = (_vp * len(maps))(*[m.data_ptr() for m in maps])
+        _check(_lib.lp_convolve_classes(self._p, ptrs, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def adjoint_class(self, cls, grad_out, out=None):
+        """C_cls^T grad_out (lp_adjoint_class)."""
+        out = self._io(grad_out, out)
+        _check(_lib.lp_adjoint_class(self._p, int(cls), ctypes.c_void_p(grad_out.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr())))
         return out
 
     def set_kernels(self, which):
@@ -386,6 +430,19 @@ def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=K
     return p
 
 
+def make_plan_classes(psfs, ny, nx, *, pitch_km=0.5, padding=None, device=None,
+                      kernels=KERNELS_AUTO, precision=PRECISION_FP32):
+    """Plan for a sum over source classes (Eq. 4), one kernel per class."""
+    psfs = [np.asarray(k) for k in psfs]
+    p = Plan(ny, nx, psfs[0].shape[0], psfs[0].shape[1], pitch_km, padding)
+    p.set_classes(len(psfs))
+    p.set_kernels(kernels)
+    p.set_precision(precision)
+    p.bind(device=device)
+    p.set_kernels_classes(psfs)
+    return p
+
+
 def _autograd():
     import torch
 
@@ -401,15 +458,37 @@ def _autograd():
         def backward(ctx, grad_s):
             return ctx.plan.adjoint(grad_s.contiguous()), None
 
-    return LPConvolve
+    class LPConvolveClasses(torch.autograd.Function):
+        """B = sum_t C_t(L_t); grad L_t = C_t^T(grad B) (lp_adjoint_class)."""
+
+        @staticmethod
+        def forward(ctx, plan, *maps):
+            ctx.plan = plan
+            return plan.convolve_classes([m.contiguous() for m in maps])
+
+        @staticmethod
+        def backward(ctx, grad_b):
+            g = grad_b.contiguous()
+            return (None,) + tuple(ctx.plan.adjoint_class(t, g) for t in range(ctx.plan.classes))
+
+    return LPConvolve, LPConvolveClasses
 
 
 _LPConvolve = None
+_LPConvolveClasses = None
 
 
 def convolve(radiance, plan):
     """Differentiable "same" convolution through the plan."""
-    global _LPConvolve
+    global _LPConvolve, _LPConvolveClasses
     if _LPConvolve is None:
-        _LPConvolve = _autograd()
+        _LPConvolve, _LPConvolveClasses = _autograd()
     return _LPConvolve.apply(radiance, plan)
+
+
+def convolve_classes(maps, plan):
+    """Differentiable class sum of Eq. 4 through a plan of len(maps) classes."""
+    global _LPConvolve, _LPConvolveClasses
+    if _LPConvolve is None:
+        _LPConvolve, _LPConvolveClasses = _autograd()
+    return _LPConvolveClasses.apply(plan, *maps)

@@ -139,8 +139,9 @@ CONTINENTAL = Workload("continental-16384x16384-psf2001-p18432", 16384, 16384, 2
                        18432, 18432, 0.5, 1002)
 ADJOINT = Workload("adjoint-2048x2048-psf801-p2880", 2048, 2048, 801, 801, 2880, 2880, 0.5, 1004)
 BATCHED_SEED = 1003
+CLASSES = Workload("classes-3x4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 5400, 5400, 0.5, 1005)
 
-WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT)}
+WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT, CLASSES)}
 
 
 def small_inputs(seed=SMALL.seed):
@@ -211,6 +212,21 @@ def batched_inputs(seed=BATCHED_SEED, n_tiles=64, side=(512, 3072), half=600):
         tiles.append(bands)
     psfs = [psf_powexp(half, e, s, 0.5, radius_km=300.0) for (s, e) in BATCHED_PSFS]
     return tiles, psf_ids.astype(np.int32), psfs
+
+
+# (scale km, exponent) of the three source classes' kernels
+CLASS_PSFS = ((60.0, 2.3), (80.0, 2.5), (110.0, 2.7))
+
+
+def classes_inputs(seed=CLASSES.seed, n=4096, half=600):
+    """Three source classes (Eq. 4) over the country-sized grid: each class
+    is its own city-cluster map (400 blobs, sigma 2-40 px, 5% background,
+    own seed stream) with its own kernel d^-a exp(-d/s), (s, a) from
+    CLASS_PSFS, cut to a 300 km disk.  Returns (maps, kernels)."""
+    rng = np.random.default_rng(seed)
+    maps = [radiance_map(n, n, 400, 0.05, (2.0, 40.0), rng) for _ in CLASS_PSFS]
+    kernels = [psf_powexp(half, a, s_km, 0.5, radius_km=300.0) for (s_km, a) in CLASS_PSFS]
+    return maps, kernels
 
 
 def sample_pixels(R, n, rng, *, n_bright=None, K=None):

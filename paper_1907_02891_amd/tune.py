@@ -27,7 +27,8 @@ def cache_path():
 
 def plan_key(plan):
     py, px = plan.padding
-    return f"{plan.ny}x{plan.nx}/k{plan.ky}x{plan.kx}/p{py}x{px}/form{plan.form}"
+    cls = f"/classes{plan.classes}" if plan.classes > 1 else ""
+    return f"{plan.ny}x{plan.nx}/k{plan.ky}x{plan.kx}/p{py}x{px}/form{plan.form}{cls}"
 
 
 def _load_cache():
@@ -51,12 +52,19 @@ def _save_cache(c):
 
 
 def _stage_time(plan, x, out, stage, reps, warmup, adjoint=False):
-    run = plan.adjoint if adjoint else plan.convolve
+    if plan.classes > 1:  # x: one map per class
+        def run():
+            plan.convolve_classes(x, out=out)
+    else:
+        f = plan.adjoint if adjoint else plan.convolve
+
+        def run():
+            f(x, out=out)
     for _ in range(warmup):
-        run(x, out=out)
+        run()
     plan.timing(True)
     for _ in range(reps):
-        run(x, out=out)
+        run()
     ms, calls = plan.stage_ms()
     plan.timing(False)
     if stage == lp.STAGE_ROWS:
@@ -66,12 +74,15 @@ def _stage_time(plan, x, out, stage, reps, warmup, adjoint=False):
 
 def autotune(plan, x=None, out=None, *, reps=20, warmup=3, use_cache=True, verbose=False):
     """Pick the fastest variant of each stage for this plan (bound, with its
-    kernel spectrum).  Returns {stage name: {"variant", "ms", "all": [...]}}."""
+    kernel spectra).  x: a map, or for a plan of several source classes a list
+    of one map per class.  Returns {stage name: {"variant", "ms", "all":
+    [...]}}."""
     import torch
     if x is None:
-        x = torch.rand(plan.ny, plan.nx, device=plan.workspace.device)
+        x = [torch.rand(plan.ny, plan.nx, device=plan.workspace.device) for _ in range(plan.classes)]
+        x = x[0] if plan.classes == 1 else x
     if out is None:
-        out = torch.empty_like(x)
+        out = torch.empty_like(x[0] if isinstance(x, (list, tuple)) else x)
     key = plan_key(plan)
     cache = _load_cache() if use_cache else {}
     report = {}

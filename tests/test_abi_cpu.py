@@ -184,3 +184,35 @@ def test_precision_modes_host_side():
     assert p.precision == lp.PRECISION_FP32
     assert lib.lp_plan_precision(None) == -1
     assert lib.lp_plan_set_precision(None, 1) == lp.LP_E_INVALID
+
+
+def test_class_plan_host_side():
+    lib = lp.raw()
+    p = lp.Plan(300, 200, 31, 21)
+    one = p.workspace_bytes
+    for bad in (0, -1, lp.MAX_CLASSES + 1):
+        with pytest.raises(lp.LPError) as ei:
+            p.set_classes(bad)
+        assert ei.value.code == lp.LP_E_INVALID
+    assert p.classes == 1
+    p.set_classes(3)
+    assert p.classes == 3 and p.workspace_bytes > 2 * one
+    # single-class entry points refuse a plan of several classes, before any
+    # device work
+    K = np.ones((31, 21))
+    fake = ctypes.c_void_p(256)
+    assert lib.lp_kernel_spectrum(p.handle, K.ctypes.data_as(ctypes.POINTER(ctypes.c_double))) == lp.LP_E_STATE
+    assert lib.lp_convolve(p.handle, fake, fake) == lp.LP_E_STATE
+    assert lib.lp_adjoint(p.handle, fake, fake) == lp.LP_E_STATE
+    maps = (ctypes.c_void_p * 3)(256, 256, 256)
+    assert lib.lp_convolve_classes(p.handle, None, fake) == lp.LP_E_INVALID
+    assert lib.lp_convolve_classes(p.handle, maps, None) == lp.LP_E_INVALID
+    assert lib.lp_convolve_classes(p.handle, maps, fake) == lp.LP_E_NOMEM  # unbound
+    holes = (ctypes.c_void_p * 3)(256, None, 256)
+    assert lib.lp_convolve_classes(p.handle, holes, fake) == lp.LP_E_INVALID
+    assert lib.lp_adjoint_class(p.handle, 3, fake, fake) == lp.LP_E_INVALID
+    assert lib.lp_adjoint_class(p.handle, -1, fake, fake) == lp.LP_E_INVALID
+    assert lib.lp_kernel_spectra(p.handle, None) == lp.LP_E_INVALID
+    assert lib.lp_plan_classes(None) == -1
+    p.set_classes(1)
+    assert p.workspace_bytes == one

@@ -108,8 +108,40 @@ constexpr int first_factor(int r)
 
 constexpr bool is_base_radix(int r) { return r == 1 || r == 2 || r == 3 || r == 4 || r == 5 || r == 8; }
 
+// Largest power of p dividing r.
+constexpr int pow_part(int r, int p)
+{
+    int q = 1;
+    while (r % p == 0) { r /= p; q *= p; }
+    return q;
+}
+
+// A factor A of r with gcd(A, r / A) = 1 and 1 < A < r (the power of 2, else
+// the power of 3), or 0 if r is a prime power.
+constexpr int coprime_factor(int r)
+{
+    const int a = pow_part(r, 2);
+    if (a > 1 && a < r) return a;
+    const int b = pow_part(r, 3);
+    if (b > 1 && b < r) return b;
+    return 0;
+}
+
+// y with x y = 1 mod m (m >= 2, gcd(x, m) = 1).
+constexpr int inv_mod(int x, int m)
+{
+    for (int y = 1; y < m; ++y)
+        if ((x * y) % m == 1) return y;
+    return 0;
+}
+
 // In-place R-point DFT of x[0..R-1] (forward sign -, inverse +, unnormalised).
-// Composite R = A * B: n = B a + b, k = k1 + A k2;
+// R = A * B with gcd(A, B) = 1 (prime-factor algorithm, Good-Thomas): with
+// n = (B a + A b) mod R and k the residue with k = k1 mod A, k = k2 mod B,
+// the kernel w_R^{nk} splits into w_A^{a k1} w_B^{b k2}, so y is a plain
+// A x B two-dimensional DFT with no twiddle factors; all index maps are
+// compile-time constants.
+// Otherwise (a prime power) Cooley-Tukey: n = B a + b, k = k1 + A k2;
 // y[k1 + A k2] = sum_b w_B^{b k2} [ w_R^{b k1} sum_a x[B a + b] w_A^{a k1} ].
 template <int R, bool INV>
 __device__ __forceinline__ void dftc(float2 *x)
@@ -117,6 +149,25 @@ __device__ __forceinline__ void dftc(float2 *x)
     if constexpr (R == 1) {
     } else if constexpr (is_base_radix(R)) {
         dft<R, INV>(x);
+    } else if constexpr (coprime_factor(R) != 0) {
+        constexpr int A = coprime_factor(R), B = R / A;
+        constexpr int EA = B * inv_mod(B % A, A), EB = A * inv_mod(A % B, B);  // CRT idempotents
+        float2 t[A][B];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) t[a][b] = x[(B * a + A * b) % R];
+            dftc<B, INV>(t[a]);
+        }
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) {
+            float2 w[A];
+#pragma unroll
+            for (int a = 0; a < A; ++a) w[a] = t[a][k2];
+            dftc<A, INV>(w);
+#pragma unroll
+            for (int k1 = 0; k1 < A; ++k1) x[(k1 * EA + k2 * EB) % R] = w[k1];
+        }
     } else {
         constexpr int A = first_factor(R), B = R / A;
         float2 t[R];

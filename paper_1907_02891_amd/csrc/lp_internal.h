@@ -165,7 +165,14 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 192, 15, 15, 12, 2, 3, 0},
     {2700, 192, 15, 15, 12, 1, 3, 0},
     {2700, 128, 15, 15, 12, 2, 3, 0},
+    {2700, 128, 15, 15, 12, 4, 2, 1},
+    {2700, 128, 15, 15, 12, 4, 2, 0},
+    {2700, 128, 15, 15, 12, 6, 2, 1},
+    {2700, 96, 12, 15, 15, 4, 2, 1},
     {9216, 384, 16, 24, 24, 1, 2, 1},
+    {9216, 384, 16, 24, 24, 2, 2, 1},
+    {9216, 384, 16, 24, 24, 2, 2, 0},
+    {9216, 256, 16, 24, 24, 2, 2, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
     {1440, 128, 12, 12, 10, 2, 3, 0},
     {256, 64, 8, 8, 4, 4, 6, 1},

@@ -266,11 +266,14 @@ void layout(lp_plan *p)
 // >= min(ny, 256) workgroups).
 void choose_shape(lp_plan *p)
 {
-    // Column-major intermediate (one column = one contiguous run of ny
-    // values); one column per workgroup of the column stage.
-    const int logc = 0;
+    // Intermediate with C = 2 interleaved columns when two padded columns fit
+    // one workgroup's LDS (the generic column kernel then takes a block of
+    // two; the specialised one still one column per workgroup): each row of a
+    // row-stage tile then writes and reads 16-byte runs instead of 8-byte ones.
+    // Otherwise column-major (C = 1).
+    const int logc = (p->h >= 2 && 2 * p->py * 8 <= lp::kLdsBytes) ? 1 : 0;
     p->logc = logc;
-    p->nblk = p->h;
+    p->nblk = (p->h + (int64_t{1} << logc) - 1) >> logc;
     int logb = 0;
     for (int l = 4; l >= 0; --l) {
         const int64_t B = int64_t{1} << l;
@@ -420,6 +423,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         const float2 *twr = reinterpret_cast<const float2 *>(p->ws + p->off_twr);
         rr.ny = static_cast<int32_t>(p->ny);
         rr.nx = static_cast<int32_t>(p->nx);
+        rr.lc = p->logc;
         rr.rtw = ra.rtw;
         rr.tw_f1 = twr + p->twr_off[0];
         rr.tw_f2 = twr + p->twr_off[1];
@@ -438,6 +442,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
         cr.ny = static_cast<int32_t>(p->ny);
         cr.ku = ca.ku;
+        cr.lc = p->logc;
         cr.kh = ca.kh;
         cr.classes = nin;
         cr.w_stride = ca.w_stride;

@@ -117,6 +117,7 @@ constexpr int kNumColSpecs = sizeof kColSpecs / sizeof kColSpecs[0];
 struct ColRegArgs {
     int32_t ny;          // stored rows per column
     int32_t ku;          // stored spectrum rows per column (n or n/2+1)
+    int32_t lc;          // log2 of the column interleave C of the intermediate and spectrum
     const void *kh;      // column-major spectrum (float real quadrant or float2)
     int32_t classes;     // source classes summed before the inverse (class-sum kernels)
     int64_t w_stride;    // float2 elements from one class's intermediate to the next
@@ -189,6 +190,7 @@ constexpr int kNumRowSpecs = sizeof kRowSpecs / sizeof kRowSpecs[0];
 
 struct RowRegArgs {
     int32_t ny, nx;
+    int32_t lc;          // log2 of the column interleave C of the intermediate
     const float2 *rtw;   // exp(-2 pi i k / Px), 0 <= k <= M
     const float2 *tw_f1, *tw_f2, *tw_i1, *tw_i2;  // as in ColRegArgs, for length M
 };

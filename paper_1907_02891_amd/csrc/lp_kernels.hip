@@ -454,7 +454,10 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
         ny = it.ny;
         a.kh = it.kh;
     }
-    float2 *col = W + static_cast<int64_t>(v) * ny;
+    // intermediate with C = 2^lc interleaved columns: element i of column v
+    // at ((v / C) * ny + i) * C + v % C, the spectrum likewise with ku rows
+    const int lc = a.lc, cm = (1 << lc) - 1;
+    float2 *col = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
 
     // forward transform of one column and product with one spectrum, left in
     // x2 in the order the inverse's first pass takes it
@@ -468,7 +471,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                     for (int j = 0; j < R0; ++j) {
                         const int n = i + j * F0::NB;
-                        x0[s][j] = (n < ny) ? src[n] : make_float2(0.f, 0.f);
+                        x0[s][j] = (n < ny) ? src[n << lc] : make_float2(0.f, 0.f);
                     }
                 }
             }
@@ -495,17 +498,19 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
                 const int i = tt + s * TF;
                 if (F2::NB % TF == 0 || i < F2::NB) {
                     if constexpr (FORM == 1) {
-                        const float *kq = static_cast<const float *>(kh) + static_cast<int64_t>(v) * a.ku;
+                        const float *kq = static_cast<const float *>(kh) +
+                                          ((static_cast<int64_t>(v >> lc) * a.ku) << lc) + (v & cm);
 #pragma unroll
                         for (int j = 0; j < R2; ++j) {
                             const int u = i + j * F2::NB;
-                            x2[s][j] = cscale(x2[s][j], kq[(2 * u <= N) ? u : N - u]);
+                            x2[s][j] = cscale(x2[s][j], kq[((2 * u <= N) ? u : N - u) << lc]);
                         }
                     } else {
-                        const float2 *kc = static_cast<const float2 *>(kh) + static_cast<int64_t>(v) * N;
+                        const float2 *kc = static_cast<const float2 *>(kh) +
+                                           ((static_cast<int64_t>(v >> lc) * N) << lc) + (v & cm);
 #pragma unroll
                         for (int j = 0; j < R2; ++j) {
-                            const float2 k = kc[i + j * F2::NB];
+                            const float2 k = kc[(i + j * F2::NB) << lc];
                             x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
                         }
                     }
@@ -554,7 +559,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                 for (int j = 0; j < R0; ++j) {
                     const int n = i + j * I2::NB;
-                    if (n < ny) col[n] = y2[s][j];
+                    if (n < ny) col[n << lc] = y2[s][j];
                 }
             }
         }
@@ -762,26 +767,29 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
                 dftc<R2, false>(z2);
             }
             if (rv) {
-                float2 *dst = W + row;
+                // X[k] of this row at ((k / C) * ny + row) * C + k % C
+                const int lc = a.lc, cm = (1 << lc) - 1;
+                float2 *dst = W + (static_cast<int64_t>(row) << lc);
+                auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
                 if (i1 == 0) {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k = j * NB;
-                        dst[k * ny] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+                        dst[at(k)] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
                     }
-                    dst[static_cast<int64_t>(M) * ny] = r2c_split(z1[0], z1[0], a.rtw[M]);
+                    dst[at(M)] = r2c_split(z1[0], z1[0], a.rtw[M]);
                 } else if (!two) {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k = i1 + j * NB;
-                        dst[k * ny] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+                        dst[at(k)] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k1 = i1 + j * NB, k2 = i2 + j * NB;
-                        dst[k1 * ny] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
-                        dst[k2 * ny] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                        dst[at(k1)] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
+                        dst[at(k2)] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
                     }
                 }
             }
@@ -858,7 +866,10 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         const bool two = pairer && (i2 != i1) && (i2 < NB);
         const int row = tile * B + b;
         const bool rv = row < a.ny;
-        const float2 *src = W + (rv ? row : 0);
+        // X[k] of this row at ((k / C) * ny + row) * C + k % C
+        const int lc = a.lc, cm = (1 << lc) - 1;
+        const float2 *src = W + (static_cast<int64_t>(rv ? row : 0) << lc);
+        auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
 #pragma unroll
         for (int j = 0; j < R2; ++j) {
             xa[j] = make_float2(0.f, 0.f);
@@ -867,12 +878,12 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         xm = make_float2(0.f, 0.f);
         if (rv && pairer) {
 #pragma unroll
-            for (int j = 0; j < R2; ++j) xa[j] = src[static_cast<int64_t>(i1 + j * NB) * ny];
+            for (int j = 0; j < R2; ++j) xa[j] = src[at(i1 + j * NB)];
             if (two) {
 #pragma unroll
-                for (int j = 0; j < R2; ++j) xb[j] = src[static_cast<int64_t>(i2 + j * NB) * ny];
+                for (int j = 0; j < R2; ++j) xb[j] = src[at(i2 + j * NB)];
             }
-            if (i1 == 0) xm = src[static_cast<int64_t>(M) * ny];
+            if (i1 == 0) xm = src[at(M)];
         }
     };
 

@@ -266,12 +266,11 @@ void layout(lp_plan *p)
 // >= min(ny, 256) workgroups).
 void choose_shape(lp_plan *p)
 {
-    // Intermediate with C = 2 interleaved columns when two padded columns fit
-    // one workgroup's LDS (the generic column kernel then takes a block of
-    // two; the specialised one still one column per workgroup): each row of a
-    // row-stage tile then writes and reads 16-byte runs instead of 8-byte ones.
-    // Otherwise column-major (C = 1).
-    const int logc = (p->h >= 2 && 2 * p->py * 8 <= lp::kLdsBytes) ? 1 : 0;
+    // Intermediate with C = 2 interleaved columns (element i of column v at
+    // ((v / 2) * ny + i) * 2 + v % 2): each row of a row-stage tile writes and
+    // reads 16-byte runs instead of 8-byte ones; the column kernels take one
+    // column per workgroup at stride 2.
+    const int logc = p->h >= 2 ? 1 : 0;
     p->logc = logc;
     p->nblk = (p->h + (int64_t{1} << logc) - 1) >> logc;
     int logb = 0;
@@ -281,7 +280,7 @@ void choose_shape(lp_plan *p)
         if ((p->m + 1) * B * 8 <= lp::kLdsBytes && groups >= std::min<int64_t>(p->ny, 256)) { logb = l; break; }
     }
     p->logb = logb;
-    p->t_cols = threads_for(p->py << logc);
+    p->t_cols = threads_for(p->py);
     p->t_rows = threads_for(p->m << logb);
 }
 
@@ -382,7 +381,7 @@ lp::ColArgs col_args(const lp_plan *p)
     a.ny = static_cast<int32_t>(p->ny);
     a.py = static_cast<int32_t>(p->py);
     a.logc = p->logc;
-    a.nblk = static_cast<int32_t>(p->nblk);
+    a.ncols = static_cast<int32_t>(p->h);
     a.ku = static_cast<int32_t>(p->form == LP_FORM_REAL_QUADRANT ? p->py / 2 + 1 : p->py);
     a.fy = p->fy;
     a.tw = reinterpret_cast<const float2 *>(p->ws + p->off_twy);
@@ -626,7 +625,7 @@ int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
 {
     clear_error();
     if (!p) return fail(LP_E_INVALID, "null plan");
-    if (cols_per_group) *cols_per_group = 1 << p->logc;
+    if (cols_per_group) *cols_per_group = 1;
     if (rows_per_group)
         *rows_per_group = (p->row_spec >= 0 && p->variant == 0 && p->precision == LP_PRECISION_FP32)
                               ? lp::row_spec_rows(p->row_spec)

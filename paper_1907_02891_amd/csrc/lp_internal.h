@@ -52,8 +52,8 @@ struct RowArgs {
 struct ColArgs {
     int32_t ny;         // stored rows of the intermediate
     int32_t py;         // padded column length
-    int32_t logc;       // log2 columns per workgroup (= per block)
-    int32_t nblk;
+    int32_t logc;       // log2 of the column interleave C of the intermediate and spectrum
+    int32_t ncols;      // columns (one per workgroup)
     int32_t ku;         // stored spectrum rows per block (py or py/2+1)
     FftDesc fy;
     const float2 *tw;

@@ -11,12 +11,12 @@
 //                (Eq. 9), inverse transform, keep rows < ny (in place in W);
 //   k_rows_c2r   inverse complex-to-real transform of each row, keep columns
 //                < nx (the crop).
-// Blocked intermediate layout: column v of row i sits at
+// Intermediate layout: column v of row i sits at
 //   W[((v >> logc) * ny + i) << logc | (v & (C-1))],
-// so one column block (C adjacent columns, all ny rows) is one contiguous
-// run: the column stage reads and writes it with unit stride, and the row
-// stages touch C*B*8-byte runs (B rows per workgroup).
-//
+// C = 2^logc interleaved columns (C = 2 for every plan with two or more
+// stored columns): a row stage with B rows per workgroup touches C*B*8-byte
+// runs, the column stage reads and writes one column at stride C (the
+// workgroup of the neighbouring column takes the other half of each line).
 // Real transforms use the half-length trick: z[n] = x[2n] + i x[2n+1] is
 // transformed at length M = Px/2 and split with exp(-2 pi i k/Px).
 #include "fft_lds.h"
@@ -77,8 +77,8 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
 }
 
 // ---------------------------------------------------------------- columns
-// FORM 1: real even spectrum, one quadrant stored, (py/2+1) rows per block.
-// FORM 2: complex spectrum, py rows per block.  CONJ: use conj(Khat) (the
+// One column per workgroup.  FORM 1: real even spectrum, one quadrant stored
+// (py/2+1 rows per column).  FORM 2: complex spectrum, py rows per column.  CONJ: use conj(Khat) (the
 // transposed operator).  ACC > 0: several source classes (Eq. 4); class t's
 // block sits a.w_stride elements after class 0's and its spectrum
 // a.kh_stride bytes after class 0's; the products are summed in registers
@@ -88,22 +88,22 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
 {
     extern __shared__ float2 lds[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int vb = xcd_tile(blockIdx.x, gridDim.x);
-    const int C = 1 << a.logc;
-    const int py = a.py;
-    const int total = py << a.logc;
-    const int stored = a.ny << a.logc;
-    float2 *blk = W + static_cast<int64_t>(vb) * stored;
+    const int v = xcd_tile(blockIdx.x, gridDim.x);
+    const int py = a.py, ny = a.ny;
+    // element i of column v at ((v / C) * ny + i) * C + v % C (C = 2^logc);
+    // the spectrum likewise with ku rows
+    const int lc = a.logc, cm = (1 << lc) - 1;
+    float2 *col = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
 
-    // spectrum value of element e of this block for one class
+    // product of element e of this column with one class's spectrum
     auto spec = [&](const void *kh, int e, float2 x) {
         if constexpr (FORM == 1) {
-            const float *kq = static_cast<const float *>(kh) + static_cast<int64_t>(vb) * (a.ku << a.logc);
-            const int u = e >> a.logc, c = e & (C - 1);
-            const int uq = (2 * u <= py) ? u : py - u;
-            return cscale(x, kq[(uq << a.logc) + c]);
+            const float *kq = static_cast<const float *>(kh) + ((static_cast<int64_t>(v >> lc) * a.ku) << lc) + (v & cm);
+            const int uq = (2 * e <= py) ? e : py - e;
+            return cscale(x, kq[uq << lc]);
         } else {
-            const float2 k = (static_cast<const float2 *>(kh) + static_cast<int64_t>(vb) * total)[e];
+            const float2 k = (static_cast<const float2 *>(kh) + ((static_cast<int64_t>(v >> lc) * py) << lc) +
+                              (v & cm))[e << lc];
             return CONJ ? cmulc(x, k) : cmul(x, k);
         }
     };
@@ -113,37 +113,37 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
 #pragma unroll
         for (int q = 0; q < ACC; ++q) acc[q] = make_float2(0.f, 0.f);
         for (int t = 0; t < a.classes; ++t) {
-            const float2 *src = blk + t * a.w_stride;
+            const float2 *src = col + t * a.w_stride;
             const void *kh = static_cast<const char *>(a.kh) + t * a.kh_stride;
             __syncthreads();  // the previous class's products are all read
-            for (int e = tid; e < total; e += nt)
-                lds[e] = (e < stored) ? src[e] : make_float2(0.f, 0.f);
+            for (int e = tid; e < py; e += nt)
+                lds[e] = (e < ny) ? src[e << lc] : make_float2(0.f, 0.f);
             __syncthreads();
-            lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, opaque_v(tid), nt, a.mf);
+            lds_fft<false, SPLIT>(lds, a.fy, 0, a.tw, opaque_v(tid), nt, a.mf);
             const int t0 = opaque_v(tid);
 #pragma unroll
             for (int q = 0; q < ACC; ++q) {
                 const int e = t0 + q * nt;
-                if (e < total) acc[q] = cadd(acc[q], spec(kh, e, lds[e]));
+                if (e < py) acc[q] = cadd(acc[q], spec(kh, e, lds[e]));
             }
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < ACC; ++q) {
             const int e = tid + q * nt;
-            if (e < total) lds[e] = acc[q];
+            if (e < py) lds[e] = acc[q];
         }
     } else {
-        for (int e = tid; e < total; e += nt)
-            lds[e] = (e < stored) ? blk[e] : make_float2(0.f, 0.f);
+        for (int e = tid; e < py; e += nt)
+            lds[e] = (e < ny) ? col[e << lc] : make_float2(0.f, 0.f);
         __syncthreads();
-        lds_fft<false, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
-        for (int e = tid; e < total; e += nt) lds[e] = spec(a.kh, e, lds[e]);
+        lds_fft<false, SPLIT>(lds, a.fy, 0, a.tw, tid, nt, a.mf);
+        for (int e = tid; e < py; e += nt) lds[e] = spec(a.kh, e, lds[e]);
     }
     __syncthreads();
-    lds_fft<true, SPLIT>(lds, a.fy, a.logc, a.tw, tid, nt, a.mf);
+    lds_fft<true, SPLIT>(lds, a.fy, 0, a.tw, tid, nt, a.mf);
 
-    for (int e = tid; e < stored; e += nt) blk[e] = lds[e];
+    for (int e = tid; e < ny; e += nt) col[e << lc] = lds[e];
 }
 
 // ------------------------------------------------------------------- rows inv
@@ -342,7 +342,7 @@ static void launch_cols_split(float2 *W, const ColArgs &a, int form, bool conj_k
                               dim3 t, size_t lds, hipStream_t s)
 {
     // class sums: 8 accumulators per thread when they suffice, else kEltsPerThread
-    if (sum && (a.py << a.logc) <= 8 * static_cast<int>(t.x))
+    if (sum && a.py <= 8 * static_cast<int>(t.x))
         launch_cols_sum<SPLIT, 8>(W, a, form, g, t, lds, s);
     else if (sum)
         launch_cols_sum<SPLIT, kEltsPerThread>(W, a, form, g, t, lds, s);
@@ -358,9 +358,9 @@ hipError_t launch_cols_conv(float2 *W, const ColArgs &a, int form, bool conj_k, 
                             hipStream_t s, bool class_sum)
 {
     if (class_sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
-    if (threads * kEltsPerThread < (a.py << a.logc)) return hipErrorInvalidValue;
-    const size_t lds = static_cast<size_t>(a.py) << a.logc << 3;
-    const dim3 g(a.nblk), t(threads);
+    if (threads * kEltsPerThread < a.py) return hipErrorInvalidValue;
+    const size_t lds = static_cast<size_t>(a.py) << 3;
+    const dim3 g(a.ncols), t(threads);
     switch (a.fy.split) {
         case 1: launch_cols_split<1>(W, a, form, conj_k, class_sum, g, t, lds, s); break;
         case 2: launch_cols_split<2>(W, a, form, conj_k, class_sum, g, t, lds, s); break;

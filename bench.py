@@ -128,6 +128,8 @@ def main():
                          "matrix cores with FP16 hi+lo / BF16 x3 split operands")
     ap.add_argument("--kernels", default="auto", choices=["auto", "generic"],
                     help="generic: LDS-staged kernels only (no specialised register kernels)")
+    ap.add_argument("--variants", default=None,
+                    help="ROWS,COLUMNS: run these specialised variants instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -166,7 +168,11 @@ def main():
     y = torch.empty_like(x)
     t0 = time.perf_counter()
     tuning = None
-    if not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
+    if args.variants:
+        for st, k in zip((lp.STAGE_ROWS, lp.STAGE_COLUMNS), args.variants.split(",")):
+            if plan.variant_count(st) > 0:
+                plan.set_variant(st, int(k))
+    elif not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
         from paper_1907_02891_amd import tune
         tuning = tune.autotune(plan, x, y, use_cache=False)
     t_tune = time.perf_counter() - t0

@@ -81,26 +81,41 @@ def read_pmc(src_hash):
     return (f + w) * 1024.0
 
 
-def cpu_baseline(R, K, budget_s):
-    """The FP64 oracle (as it stands) on a seeded pixel sample, host cores."""
+def cpu_leg(oracle_at, n_total, gpu_at, budget_s, unit, what):
+    """The CPU baseline: the FP64 oracle as it stands, timed on the host cores
+    on a uniformly drawn sample of output units sized to about budget_s of
+    work; its values on that sample are also compared with the GPU result at
+    the same units (relative L2 and max error over max |value|).
+    oracle_at(idx) -> FP64 values at flat unit indices; gpu_at(idx) -> the
+    GPU's values there."""
     import oracle
     rng = np.random.default_rng(99)
-    Rd = R.astype(np.float64)
-    n = 64
+    n = 16
     for _ in range(2):  # the first round also starts the thread pool
         t0 = time.perf_counter()
-        oracle.conv_same_pixels(Rd, K, rng.choice(R.size, n, replace=False))
+        oracle_at(np.sort(rng.choice(n_total, min(n, n_total), replace=False)))
         dt = time.perf_counter() - t0
-        n = int(max(64, min(R.size, n * min(budget_s, 2.0) / max(dt, 1e-6))))
-    n = int(max(64, min(R.size, n * budget_s / 2.0)))
-    idx = rng.choice(R.size, n, replace=False)
+        n = int(max(16, min(n_total, n * min(budget_s, 2.0) / max(dt, 1e-6))))
+    n = int(max(16, min(n_total, n * budget_s / 2.0)))
+    idx = np.sort(rng.choice(n_total, n, replace=False))
     t0 = time.perf_counter()
-    oracle.conv_same_pixels(Rd, K, idx)
+    ref = oracle_at(idx)
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "output pixels/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{n} uniformly drawn output pixels of the same map, FP64 direct sum "
-                      f"over the {K.shape[0]}x{K.shape[1]} kernel, {dt:.1f} s"}
+    got = gpu_at(idx)
+    return {"value": n / dt, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} uniformly drawn {what}, {dt:.1f} s",
+            "parity": {"units": int(n), "rel_l2": oracle.rel_l2(got, ref),
+                       "max_err_frac": oracle.max_err_frac(got, ref)}}
+
+
+def cpu_baseline(R, K, budget_s, y):
+    """The oracle's direct FP64 sum of the same map on sampled output pixels."""
+    import oracle
+    Rd = R.astype(np.float64)
+    yh = y.cpu().numpy().ravel()
+    return cpu_leg(lambda idx: oracle.conv_same_pixels(Rd, K, idx), R.size, lambda idx: yh[idx],
+                   budget_s, "output pixels/s",
+                   f"output pixels of the same map, FP64 direct sum over the {K.shape[0]}x{K.shape[1]} kernel")
 
 
 PRECISIONS = {"fp32": (0, "f32", "FP32 FFT convolution"),
@@ -116,10 +131,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="country",
-                    choices=["country", "small", "adjoint", "continental", "batched", "classes"])
+                    choices=["country", "small", "adjoint", "continental", "batched", "classes", "reproject",
+                             "bands"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--check", type=int, default=256, help="sampled parity pixels (0: off)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (variant 0 of each stage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte calibration)")
@@ -142,6 +157,10 @@ def main():
         return bench_batched(args)
     if args.workload == "classes":
         return bench_classes(args)
+    if args.workload == "reproject":
+        return bench_reproject(args)
+    if args.workload == "bands":
+        return bench_bands(args)
     wl, make_inputs = workloads()[args.workload]
     t0 = time.perf_counter()
     R, K = make_inputs()
@@ -237,16 +256,6 @@ def main():
         "kernel_source": src_hash,
     }
 
-    if args.check > 0:
-        import oracle
-        rng = np.random.default_rng(5)
-        from paper_1907_02891_amd import synth
-        idx = synth.sample_pixels(R, args.check, rng)
-        got = y.cpu().numpy().ravel()[idx]
-        ref = oracle.conv_same_pixels(R, K, idx)
-        out["parity_sample"] = {"pixels": int(idx.size), "rel_l2": oracle.rel_l2(got, ref),
-                                "max_err_frac": oracle.max_err_frac(got, ref)}
-
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -255,7 +264,7 @@ def main():
         out["copy_calibration_bytes"] = 2 * a.numel() * 4
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(R, K, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(R, K, args.cpu_budget, y)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     out["paper_context"] = {"px_per_s": 3.28e6, "hardware": "Matlab R2011a, Intel Core i7 2.40 GHz",
                             "workload": "11920x11804 map, ZSB kernel, incl. file output"}
@@ -266,7 +275,6 @@ def bench_batched(args):
     """64 tiles x 3 bands with 4 kernels: one lp_convolve_batched per step
     (HIP graph replay); value = output pixels of all maps per second."""
     import torch
-    import oracle
     from paper_1907_02891_amd import lp, synth
 
     t0 = time.perf_counter()
@@ -313,16 +321,25 @@ def bench_batched(args):
         "setup_s": {"inputs": round(t_gen, 2), "batch_spectra_and_autotune": round(t_setup, 3)},
         "autotune": [{"classes": r["classes"], "ms": round(r["ms"], 4)} for r in (tune_report or [])],
     }
-    if args.check > 0:
-        rng = np.random.default_rng(6)
-        got, ref = [], []
-        for t in rng.choice(len(maps), 8, replace=False):
-            idx = rng.choice(maps[t].size, max(4, args.check // 8), replace=False)
-            got.append(ys[t].reshape(-1).cpu().numpy()[idx])
-            ref.append(oracle.conv_same_pixels(maps[t], psfs[ids[t]], idx))
-        got, ref = np.concatenate(got), np.concatenate(ref)
-        out["parity_sample"] = {"pixels": int(got.size), "rel_l2": oracle.rel_l2(got, ref),
-                                "max_err_frac": oracle.max_err_frac(got, ref)}
+    if not args.no_cpu:
+        import oracle
+        # units: output pixels of all maps, numbered map by map
+        offs = np.cumsum([0] + [m.size for m in maps])
+        yh = [o.cpu().numpy().ravel() for o in ys]
+        md = [m.astype(np.float64) for m in maps]
+
+        def split(idx):
+            t = np.searchsorted(offs, idx, side="right") - 1
+            return [(k, idx[t == k] - offs[k]) for k in np.unique(t)]
+
+        def oracle_at(idx):
+            return np.concatenate([oracle.conv_same_pixels(md[k], psfs[ids[k]], j) for k, j in split(idx)])
+
+        def gpu_at(idx):
+            return np.concatenate([yh[k][j] for k, j in split(idx)])
+
+        out["cpu_baseline"] = cpu_leg(oracle_at, int(offs[-1]), gpu_at, args.cpu_budget, "output pixels/s",
+                                      "output pixels over all maps, FP64 direct sums with each map's kernel")
     print(json.dumps(out), flush=True)
 
 
@@ -333,7 +350,6 @@ def bench_classes(args):
     value = output pixels of the summed map per second.  Also timed: the same
     sum as three separate convolutions plus two additions."""
     import torch
-    import oracle
     from paper_1907_02891_amd import lp, synth, tune
 
     wl = synth.CLASSES
@@ -418,14 +434,146 @@ def bench_classes(args):
         "variants": {"rows": plan.variant(lp.STAGE_ROWS), "columns": plan.variant(lp.STAGE_COLUMNS),
                      "separate": [singles[0].variant(lp.STAGE_ROWS), singles[0].variant(lp.STAGE_COLUMNS)]},
     }
-    if args.check > 0:
-        rng = np.random.default_rng(7)
-        idx = synth.sample_pixels(maps[0], args.check, rng)
-        got = y.cpu().numpy().ravel()[idx]
-        ref = oracle.conv_same_classes_pixels(maps, Ks, idx)
-        out["parity_sample"] = {"pixels": int(idx.size), "rel_l2": oracle.rel_l2(got, ref),
-                                "max_err_frac": oracle.max_err_frac(got, ref)}
+    if not args.no_cpu:
+        import oracle
+        yh = y.cpu().numpy().ravel()
+        md = [m.astype(np.float64) for m in maps]
+        out["cpu_baseline"] = cpu_leg(lambda idx: oracle.conv_same_classes_pixels(md, Ks, idx), ny * nx,
+                                      lambda idx: yh[idx], args.cpu_budget, "output pixels/s",
+                                      "pixels of the summed map, FP64 direct sums over the three classes")
     print(json.dumps(out), flush=True)
+
+
+def _timed(fn, stream, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_reproject(args):
+    """Nearest-neighbour reprojection (Sec. 2.4) of a 15 arc-second
+    longitude-latitude map onto the paper's projected grid: 11920 x 11804
+    pixels of 404.4 m, transverse Mercator about -3 degrees (UTM zone 30),
+    centred at 40 N; the source covers the whole target (17-64 N, 52 W-46 E:
+    11280 x 23520 pixels).  One step = one lp_reproject_nn; value = projected
+    pixels per second."""
+    import torch
+    from paper_1907_02891_amd import lp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    step = 1.0 / 240.0
+    sg = lp.LatLonGrid(11280, 23520, 64.0 - step / 2, -52.0 + step / 2, step, step)
+    ny, nx, pitch = 11920, 11804, 0.4044
+    dg = lp.TMGrid(ny, nx, -(nx - 1) / 2 * pitch, 4430.0 + (ny - 1) / 2 * pitch, pitch, -3.0, 0.9996, 6367.0)
+    rng = np.random.default_rng(1006)
+    t0 = time.perf_counter()
+    src = torch.from_numpy(rng.random((sg.rows, sg.cols), dtype=np.float32)).to(dev)
+    t_gen = time.perf_counter() - t0
+    out = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    ms = _timed(lambda: lp.reproject_nn(src, sg, dg, out=out, stream=stream), stream, args.steps, args.warmup)
+    algo = 8 * ny * nx  # one gathered 4-byte read and one 4-byte write per projected pixel
+    res = {
+        "metric": "projected pixels/s per MI355X (nearest-neighbour transverse Mercator reprojection)",
+        "value": ny * nx / (ms * 1e-3), "unit": "projected pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 index, f32 data",
+        "data": "synthetic",
+        "config": {"workload": "reproject-15arcsec-to-11920x11804-utm30-404m", "source": [sg.rows, sg.cols],
+                   "target": [ny, nx], "pitch_km": pitch},
+        "roofline": {"bound": "hbm", "kernel": "k_reproject_nn", "achieved": round(algo / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": algo},
+        "setup_s": {"inputs": round(t_gen, 2)},
+    }
+    if not args.no_cpu:
+        from oracle import latlon as olat
+        # units: projected rows; the oracle's gather is vectorised per row
+        got = out.cpu().numpy()
+        h = src.cpu().numpy().astype(np.float64)
+        stats = {"mismatches": 0, "rounding_ties": 0}
+
+        def oracle_at(rows):
+            vals = []
+            for i in rows:
+                ref, rowf, colf = olat.reproject_nn(h, sg.lat_first_deg, sg.lon_first_deg, step, step, 1, nx,
+                                                    dg.x_first_km, dg.y_first_km - i * pitch, pitch, -3.0,
+                                                    0.9996, 6367.0)
+                tie = ((np.abs(np.abs(rowf - np.floor(rowf)) - 0.5) < 1e-9)
+                       | (np.abs(np.abs(colf - np.floor(colf)) - 0.5) < 1e-9))
+                stats["rounding_ties"] += int(tie.sum())
+                stats["mismatches"] += int((got[i][~tie[0]] != ref[0][~tie[0]].astype(np.float32)).sum())
+                vals.append(ref[0])
+            return np.concatenate(vals)
+
+        res["cpu_baseline"] = cpu_leg(oracle_at, ny, lambda rows: got[rows].ravel().astype(np.float64),
+                                      args.cpu_budget, "projected rows/s",
+                                      f"projected rows of {nx} pixels, FP64 numpy gather")
+        res["cpu_baseline"]["parity"].update(stats)
+        res["cpu_baseline"]["value_px_per_s"] = res["cpu_baseline"]["value"] * nx
+    print(json.dumps(res), flush=True)
+
+
+def bench_bands(args):
+    """Latitude-band convolution in the native longitude-latitude grid
+    (Sec. 4): a 2400 x 2400 map at 30 arc-seconds (60-40 N), 8 bands of 300
+    rows, each with the d^-2.5 exp(-d/80 km) kernel sampled for its centre
+    latitude and cut at 300 km (649 x 1007 pixels at the widest); one batched
+    call per step (slabs with halos, band rows written in place)."""
+    import torch
+    from paper_1907_02891_amd import latlon, lp, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    ny = nx = 2400
+    step = 1.0 / 120.0
+    lat_first = 60.0 - step / 2
+    edges = list(range(0, ny + 1, 300))
+    rng = np.random.default_rng(1007)
+    L = synth.radiance_map(ny, nx, 150, 0.05, (2.0, 20.0), rng)
+    half_y = int(300.0 / (latlon.EARTH_RADIUS_KM * step * np.pi / 180.0))
+    lat_min_centre = min(latlon.band_centres(edges, lat_first, step))
+    half_x = int(300.0 / (latlon.EARTH_RADIUS_KM * np.cos(np.radians(lat_min_centre)) * step * np.pi / 180.0))
+
+    def radial(d):
+        dd = np.maximum(d, 0.5 * latlon.EARTH_RADIUS_KM * step * np.pi / 180.0)
+        return np.where(d <= 300.0, dd ** -2.5 * np.exp(-dd / 80.0), 0.0)
+
+    Ks = [latlon.band_kernel(radial, c, step, step, half_y, half_x) for c in latlon.band_centres(edges, lat_first, step)]
+    t0 = time.perf_counter()
+    bands = latlon.LatitudeBands(ny, nx, edges, Ks, device=dev, stream=stream)
+    t_setup = time.perf_counter() - t0
+    x = torch.from_numpy(L).to(dev)
+    y = torch.empty_like(x)
+    ms = _timed(lambda: bands.convolve(x, out=y), stream, args.steps, args.warmup)
+    res = {
+        "metric": "output pixels/s per MI355X (latitude-band FFT convolution on the longitude-latitude grid)",
+        "value": ny * nx / (ms * 1e-3), "unit": "output pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "bands-2400x2400-30arcsec-8bands", "kernel": [2 * half_y + 1, 2 * half_x + 1],
+                   "bands": len(edges) - 1, "padding_classes": [g["padding"] for g in bands.batch.groups]},
+        "setup_s": {"band_kernels_plans_spectra": round(t_setup, 3)},
+    }
+    if not args.no_cpu:
+        from oracle import latlon as olat
+        yh = y.cpu().numpy().ravel()
+        Ld = L.astype(np.float64)
+        res["cpu_baseline"] = cpu_leg(lambda idx: olat.conv_latitude_bands_pixels(Ld, edges, Ks, idx), ny * nx,
+                                      lambda idx: yh[idx], args.cpu_budget, "output pixels/s",
+                                      "output pixels, FP64 direct sums with each row's band kernel")
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

@@ -239,6 +239,41 @@ enum { LP_PRECISION_FP32 = 0, LP_PRECISION_SPLIT_FP16 = 1, LP_PRECISION_SPLIT_BF
 int lp_plan_set_precision(lp_plan *plan, int mode);
 int lp_plan_precision(const lp_plan *plan);
 
+/* ------------------------------------------------------- reprojection --
+ * Sec. 2.4: the radiance composites come on a uniform longitude-latitude
+ * grid whose ground scale varies with latitude; the convolution needs a grid
+ * of uniform scale (shift-invariant kernel), so the map is reprojected onto a
+ * transverse Mercator (UTM-type) grid by nearest-neighbour resampling.
+ *
+ * Source grid: row r has latitude lat_first - r * dlat, column c longitude
+ * lon_first + c * dlon (degrees, pixel centres; rows run southward).
+ * Projected grid: row i has northing y_first - i * pitch, column j easting
+ * x_first + j * pitch (km from the equator and from the central meridian
+ * lon0; no false easting or northing), central scale k0, sphere radius R.
+ * Each projected pixel centre is mapped to latitude and longitude by the
+ * spherical inverse transverse Mercator (Snyder; the paper's reference for
+ * Eq. 11) and takes the nearest source pixel in (row, column) index space,
+ * halves rounded to even; 0 where that pixel lies outside the source grid.
+ * ground_area != 0 multiplies by 1 / k^2, k = k0 cosh(x / (k0 R)) (Eq. 11):
+ * the projection is conformal, so a projected cell of pitch^2 covers
+ * pitch^2 / k^2 of ground (a radiance map becomes flux per cell / pitch^2).
+ * FP64 index arithmetic.  src and dst: device FP32, row-major, not
+ * overlapping; the call enqueues one kernel on `stream` (a hipStream_t;
+ * NULL = the null stream) and returns.  Errors: LP_E_INVALID (null pointers,
+ * sizes <= 0, non-finite or non-positive steps, pitch, k0 or R), LP_E_SIZE
+ * (more than 262140 projected rows), LP_E_DEVICE. */
+typedef struct {
+    int64_t rows, cols;
+    double lat_first_deg, lon_first_deg, dlat_deg, dlon_deg;
+} lp_latlon_grid;
+typedef struct {
+    int64_t rows, cols;
+    double x_first_km, y_first_km, pitch_km;
+    double lon0_deg, k0, radius_km;
+} lp_tm_grid;
+int lp_reproject_nn(const lp_latlon_grid *src_grid, const float *src, const lp_tm_grid *dst_grid,
+                    float *dst, int ground_area, void *stream);
+
 /* ---------------------------------------------------------------- batch --
  * Many independent maps (tiles, spectral bands) convolved with a few kernels:
  * the factorable-classes case of Sec. 2.2 (Eq. 4), handled map by map.  Map t
@@ -285,6 +320,13 @@ int lp_batch_kernel_spectra(lp_batch *batch, const double *const *psfs);
  * differs from the previous call the per-map device table is re-uploaded
  * (synchronising the stream); the graph reads it and is kept. */
 int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *const *out);
+
+/* Write only rows [first, first + count) of tile `tile`'s "same" output,
+ * row first at out[tile] + 0: out[tile] then holds count x nx floats.  For
+ * overlap-save slabs (a slab convolved with its halo rows, only its own rows
+ * kept) with no copy.  Default: all ny rows.  Takes effect at the next
+ * lp_convolve_batched.  Errors: LP_E_INVALID (tile or rows out of range). */
+int lp_batch_set_output_rows(lp_batch *batch, int tile, int64_t first, int64_t count);
 
 /* Graph replay (default) or direct launches (enable = 0). */
 int lp_batch_use_graph(lp_batch *batch, int enable);

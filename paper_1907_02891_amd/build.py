@@ -7,7 +7,7 @@ import sys
 _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB = os.path.join(_HERE, "liblp.so")
-SOURCES = ["csrc/lp_api.cpp", "csrc/lp_kernels.hip"]
+SOURCES = ["csrc/lp_api.cpp", "csrc/lp_kernels.hip", "csrc/lp_reproject.hip"]
 
 # -packed-fp32-ops: keep hipcc from forming packed FP32 vector instructions.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -18,16 +18,19 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
 def build(verbose=False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(_HERE, "csrc")]
-    objs = []
-    for src in SOURCES:
+    objs, procs = [], []
+    for src in SOURCES:  # compiled in parallel
         path = os.path.join(_HERE, src)
         obj = os.path.join(_HERE, "csrc", os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
         cmd = [hipcc, *HIP_FLAGS, *inc, *lang, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    for cmd, proc in procs:
+        if proc.wait() != 0:
+            raise subprocess.CalledProcessError(proc.returncode, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

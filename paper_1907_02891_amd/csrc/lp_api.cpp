@@ -423,6 +423,8 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         rr.ny = static_cast<int32_t>(p->ny);
         rr.nx = static_cast<int32_t>(p->nx);
         rr.lc = p->logc;
+        rr.keep0 = 0;
+        rr.keep1 = static_cast<int32_t>(p->ny);
         rr.rtw = ra.rtw;
         rr.tw_f1 = twr + p->twr_off[0];
         rr.tw_f2 = twr + p->twr_off[1];
@@ -830,6 +832,46 @@ int lp_adjoint_class(lp_plan *p, int cls, const float *grad_out, float *grad_in)
     return run_path(p, &grad_out, 1, grad_in, true, cls, "lp_adjoint_class");
 }
 
+int lp_reproject_nn(const lp_latlon_grid *sg, const float *src, const lp_tm_grid *dg, float *dst,
+                    int ground_area, void *stream)
+{
+    clear_error();
+    if (!sg || !dg || !src || !dst) return fail(LP_E_INVALID, "lp_reproject_nn: null argument");
+    if (sg->rows <= 0 || sg->cols <= 0 || dg->rows <= 0 || dg->cols <= 0)
+        return fail(LP_E_INVALID, "lp_reproject_nn: grid sizes must be positive");
+    const double pos[] = {sg->dlat_deg, sg->dlon_deg, dg->pitch_km, dg->k0, dg->radius_km};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v))
+            return fail(LP_E_INVALID, "lp_reproject_nn: steps, pitch, k0 and radius must be positive and finite");
+    const double fin[] = {sg->lat_first_deg, sg->lon_first_deg, dg->x_first_km, dg->y_first_km, dg->lon0_deg};
+    for (double v : fin)
+        if (!std::isfinite(v)) return fail(LP_E_INVALID, "lp_reproject_nn: grid origins must be finite");
+    if (dg->rows > lp::reproject_max_rows())
+        return fail(LP_E_SIZE, "lp_reproject_nn: %lld projected rows beyond the maximum %lld",
+                    (long long)dg->rows, (long long)lp::reproject_max_rows());
+    lp::ReprojArgs a{};
+    a.src = src;
+    a.nlat = sg->rows;
+    a.nlon = sg->cols;
+    a.lat_first = sg->lat_first_deg;
+    a.lon_first = sg->lon_first_deg;
+    a.dlat = sg->dlat_deg;
+    a.dlon = sg->dlon_deg;
+    a.dst = dst;
+    a.ny = dg->rows;
+    a.nx = dg->cols;
+    a.x_first = dg->x_first_km;
+    a.y_first = dg->y_first_km;
+    a.pitch = dg->pitch_km;
+    a.lon0 = dg->lon0_deg;
+    a.k0 = dg->k0;
+    a.k0r = dg->k0 * dg->radius_km;
+    a.ground_area = ground_area != 0;
+    const hipError_t e = lp::launch_reproject_nn(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e, "lp_reproject_nn launch");
+    return LP_OK;
+}
+
 int lp_plan_set_classes(lp_plan *p, int n)
 {
     clear_error();
@@ -913,6 +955,7 @@ struct lp_batch {
     };
     int n = 0, n_psf = 0;
     std::vector<int64_t> ny, nx, ky, kx;
+    std::vector<int64_t> keep0, keep_n;  // output rows [keep0, keep0 + keep_n) of each map
     std::vector<int> psf;
     double pitch = 0;
     std::vector<Group> groups;
@@ -1072,6 +1115,8 @@ lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *
     b->n_psf = n_psf;
     b->pitch = pitch_km;
     b->ny.assign(ny, ny + n_tiles);
+    b->keep0.assign(n_tiles, 0);
+    b->keep_n.assign(ny, ny + n_tiles);
     b->nx.assign(nx, nx + n_tiles);
     b->psf.assign(psf_id, psf_id + n_tiles);
     b->ky.assign(ky, ky + n_psf);
@@ -1290,6 +1335,8 @@ int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const 
                 it.kh = b->ws + g.off_kh[j];
                 it.ny = static_cast<int32_t>(b->ny[t]);
                 it.nx = static_cast<int32_t>(b->nx[t]);
+                it.keep0 = static_cast<int32_t>(b->keep0[t]);
+                it.keep1 = static_cast<int32_t>(b->keep0[t] + b->keep_n[t]);
                 g.tab[g.form[j] == LP_FORM_REAL_QUADRANT ? 0 : 1].push_back(it);
             }
             for (int f = 0; f < 2; ++f)
@@ -1329,6 +1376,22 @@ int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const 
         b->graph_ok = true;
     }
     if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return fail_hip(e, "graph launch");
+    return LP_OK;
+}
+
+int lp_batch_set_output_rows(lp_batch *b, int tile, int64_t first, int64_t count)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (tile < 0 || tile >= b->n) return fail(LP_E_INVALID, "tile %d outside [0, %d)", tile, b->n);
+    if (first < 0 || count < 1 || first + count > b->ny[tile])
+        return fail(LP_E_INVALID, "tile %d: rows [%lld, %lld) outside [0, %lld)", tile, (long long)first,
+                    (long long)(first + count), (long long)b->ny[tile]);
+    if (b->keep0[tile] != first || b->keep_n[tile] != count) {
+        b->keep0[tile] = first;
+        b->keep_n[tile] = count;
+        b->tables_dirty = true;
+    }
     return LP_OK;
 }
 

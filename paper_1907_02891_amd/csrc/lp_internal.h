@@ -133,10 +133,11 @@ struct ColRegArgs {
 // size, the spectrum form and the twiddle tables).
 struct BatchItem {
     const float *in;   // radiance, ny x nx
-    float *out;        // output map, ny x nx
+    float *out;        // output rows keep0 .. keep1-1 of the map, nx wide
     float2 *w;         // intermediate, column-major, (Px/2+1) columns of ny
     const void *kh;    // spectrum of the item's kernel at this padded size
     int32_t ny, nx;
+    int32_t keep0, keep1;  // output rows [keep0, keep1) of the map, written from out[0]
 };
 
 // Index of the k-th specialisation for column length n, or -1; number of them.
@@ -191,9 +192,24 @@ constexpr int kNumRowSpecs = sizeof kRowSpecs / sizeof kRowSpecs[0];
 struct RowRegArgs {
     int32_t ny, nx;
     int32_t lc;          // log2 of the column interleave C of the intermediate
+    int32_t keep0, keep1;  // inverse: rows [keep0, keep1) are written, row r at out + (r - keep0) nx
     const float2 *rtw;   // exp(-2 pi i k / Px), 0 <= k <= M
     const float2 *tw_f1, *tw_f2, *tw_i1, *tw_i2;  // as in ColRegArgs, for length M
 };
+
+// Nearest-neighbour reprojection (lp_reproject.hip).
+struct ReprojArgs {
+    const float *src;        // nlat x nlon, row r at latitude lat_first - r dlat
+    int64_t nlat, nlon;
+    double lat_first, lon_first, dlat, dlon;  // degrees
+    float *dst;              // ny x nx, row i at northing y_first - i pitch
+    int64_t ny, nx;
+    double x_first, y_first, pitch;           // km
+    double lon0, k0, k0r;    // central meridian (degrees), central scale, k0 * R (km)
+    int32_t ground_area;     // multiply by 1 / k^2 (Eq. 11)
+};
+hipError_t launch_reproject_nn(const ReprojArgs &a, hipStream_t s);
+int64_t reproject_max_rows();
 
 int row_spec_index(int m, int k = 0);
 int row_spec_count(int m);

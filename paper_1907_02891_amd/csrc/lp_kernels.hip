@@ -855,6 +855,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         Sm = it.out;
         a.ny = it.ny;
         a.nx = it.nx;
+        a.keep0 = it.keep0;
+        a.keep1 = it.keep1;
     }
     const int ntiles = (a.ny + B - 1) / B;
     const int G = gridDim.x;
@@ -865,7 +867,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         const int i1 = tt, i2 = NB - tt;
         const bool two = pairer && (i2 != i1) && (i2 < NB);
         const int row = tile * B + b;
-        const bool rv = row < a.ny;
+        const bool rv = row >= a.keep0 && row < a.keep1;  // rows outside are not needed
         // X[k] of this row at ((k / C) * ny + row) * C + k % C
         const int lc = a.lc, cm = (1 << lc) - 1;
         const float2 *src = W + (static_cast<int64_t>(rv ? row : 0) << lc);
@@ -892,7 +894,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         const int i1 = tt, i2 = NB - tt;
         const bool two = pairer && (i2 != i1) && (i2 < NB);
         const int row = tile * B + b;
-        const bool rv = row < a.ny;
+        const bool rv = row >= a.keep0 && row < a.keep1;  // rows outside are not needed
         if (pairer) {
             float2 za[R2], zb[R2];
             if (i1 == 0) {
@@ -932,7 +934,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         I2::template twiddle<true>(y2, a.tw_i2, tt);
         I2::template butterfly<true>(y2, tt);
         if (rv) {
-            float *dst = Sm + static_cast<int64_t>(row) * a.nx;
+            float *dst = Sm + static_cast<int64_t>(row - a.keep0) * a.nx;
 #pragma unroll
             for (int s = 0; s < I2::S; ++s) {
                 const int i = tt + s * TF;
@@ -956,6 +958,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     if (t0 >= ntiles) return;
     const int tt0 = tid0 / B, b0 = tid0 % B;
     if constexpr (TPW == 1) {
+        // a tile with no row to keep does nothing (uniform over the workgroup)
+        if (t0 * B >= a.keep1 || (t0 + 1) * B <= a.keep0) return;
         float2 xa[R2], xb[R2], xm;
         load_tile(xa, xb, xm, t0, tt0, b0);
         transform(xa, xb, xm, t0, tt0, b0);

@@ -38,6 +38,23 @@ _ip = ctypes.POINTER(ctypes.c_int)
 _dp = ctypes.POINTER(ctypes.c_double)
 _fp = ctypes.POINTER(ctypes.c_float)
 
+class LatLonGrid(ctypes.Structure):
+    """lp_latlon_grid: row r at latitude lat_first - r dlat, column c at
+    longitude lon_first + c dlon (degrees)."""
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("lat_first_deg", ctypes.c_double), ("lon_first_deg", ctypes.c_double),
+                ("dlat_deg", ctypes.c_double), ("dlon_deg", ctypes.c_double)]
+
+
+class TMGrid(ctypes.Structure):
+    """lp_tm_grid: row i at northing y_first - i pitch, column j at easting
+    x_first + j pitch (km from the equator / central meridian)."""
+    _fields_ = [("rows", ctypes.c_int64), ("cols", ctypes.c_int64),
+                ("x_first_km", ctypes.c_double), ("y_first_km", ctypes.c_double),
+                ("pitch_km", ctypes.c_double), ("lon0_deg", ctypes.c_double),
+                ("k0", ctypes.c_double), ("radius_km", ctypes.c_double)]
+
+
 _SIGS = {
     "lp_last_error": ([], ctypes.c_char_p),
     "lp_version": ([], ctypes.c_char_p),
@@ -60,6 +77,8 @@ _SIGS = {
     "lp_plan_kernels": ([_vp], ctypes.c_int),
     "lp_plan_set_precision": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_set_classes": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_reproject_nn": ([ctypes.POINTER(LatLonGrid), _vp, ctypes.POINTER(TMGrid), _vp, ctypes.c_int, _vp],
+                        ctypes.c_int),
     "lp_plan_classes": ([_vp], ctypes.c_int),
     "lp_kernel_spectra": ([_vp, ctypes.POINTER(_dp)], ctypes.c_int),
     "lp_convolve_classes": ([_vp, ctypes.POINTER(_vp), _vp], ctypes.c_int),
@@ -79,6 +98,7 @@ _SIGS = {
     "lp_batch_kernel_spectra": ([_vp, ctypes.POINTER(_dp)], ctypes.c_int),
     "lp_convolve_batched": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)], ctypes.c_int),
     "lp_batch_use_graph": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_batch_set_output_rows": ([_vp, ctypes.c_int, _i64, _i64], ctypes.c_int),
     "lp_batch_group_count": ([_vp], ctypes.c_int),
     "lp_batch_group_info": ([_vp, ctypes.c_int, _i64p, ctypes.c_int], ctypes.c_int),
     "lp_batch_tile_group": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -370,13 +390,24 @@ class Batch:
         self._psfs = arrs
         return self
 
+    def set_output_rows(self, tile, first, count):
+        """Keep only rows [first, first + count) of map `tile`'s output
+        (lp_batch_set_output_rows); its output tensor is then count x nx."""
+        _check(_lib.lp_batch_set_output_rows(self._b, int(tile), int(first), int(count)))
+        if not hasattr(self, "_out_rows"):
+            self._out_rows = {}
+        self._out_rows[int(tile)] = int(count)
+
     def convolve(self, maps, outs=None):
         """maps: list of contiguous float32 CUDA tensors (shape per map)."""
         import torch
+        rows = getattr(self, "_out_rows", {})
+        oshapes = [(rows.get(t, sh[0]), sh[1]) for t, sh in enumerate(self.shapes)]
         if outs is None:
-            outs = [torch.empty_like(m) for m in maps]
-        for m, o, sh in zip(maps, outs, self.shapes):
-            if tuple(m.shape) != sh or tuple(o.shape) != sh or m.dtype != torch.float32 or not m.is_contiguous():
+            outs = [torch.empty(osh, dtype=torch.float32, device=m.device) for m, osh in zip(maps, oshapes)]
+        for m, o, sh, osh in zip(maps, outs, self.shapes, oshapes):
+            if (tuple(m.shape) != sh or tuple(o.shape) != osh or m.dtype != torch.float32 or o.dtype != torch.float32
+                    or not m.is_contiguous() or not o.is_contiguous()):
                 raise ValueError("bad map tensor")
         n = len(self.shapes)
         ins = (_vp * n)(*[m.data_ptr() for m in maps])
@@ -416,6 +447,26 @@ def spec_lengths():
         _lib.lp_batch_spec_lengths(axis, v, n)
         out.append(list(v))
     return tuple(out)
+
+
+def reproject_nn(src, src_grid, dst_grid, *, ground_area=False, out=None, stream=None):
+    """Nearest-neighbour reprojection of a longitude-latitude map onto a
+    transverse Mercator grid (lp_reproject_nn).  src: CUDA float32
+    (rows, cols) tensor; src_grid: LatLonGrid; dst_grid: TMGrid."""
+    import torch
+    if not (isinstance(src, torch.Tensor) and src.is_cuda and src.dtype == torch.float32
+            and src.is_contiguous() and tuple(src.shape) == (src_grid.rows, src_grid.cols)):
+        raise ValueError("src must be a contiguous CUDA float32 tensor of the source grid's shape")
+    if out is None:
+        out = torch.empty((dst_grid.rows, dst_grid.cols), dtype=torch.float32, device=src.device)
+    elif not (out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+              and tuple(out.shape) == (dst_grid.rows, dst_grid.cols)):
+        raise ValueError("bad output tensor")
+    st = torch.cuda.current_stream(src.device) if stream is None else stream
+    _check(_lib.lp_reproject_nn(ctypes.byref(src_grid), ctypes.c_void_p(src.data_ptr()),
+                                ctypes.byref(dst_grid), ctypes.c_void_p(out.data_ptr()),
+                                int(bool(ground_area)), _stream_ptr(st)))
+    return out
 
 
 def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO,

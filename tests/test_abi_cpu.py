@@ -216,3 +216,45 @@ def test_class_plan_host_side():
     assert lib.lp_plan_classes(None) == -1
     p.set_classes(1)
     assert p.workspace_bytes == one
+
+
+def test_reprojection_argument_errors():
+    lib = lp.raw()
+    sg = lp.LatLonGrid(10, 10, 40.0, -3.0, 0.01, 0.01)
+    dg = lp.TMGrid(10, 10, 0.0, 4400.0, 1.0, -3.0, 0.9996, 6367.0)
+    fake = ctypes.c_void_p(256)
+    ok = lambda s, d: lib.lp_reproject_nn(ctypes.byref(s), fake, ctypes.byref(d), fake, 0, None)
+    assert lib.lp_reproject_nn(None, fake, ctypes.byref(dg), fake, 0, None) == lp.LP_E_INVALID
+    assert lib.lp_reproject_nn(ctypes.byref(sg), None, ctypes.byref(dg), fake, 0, None) == lp.LP_E_INVALID
+    assert lib.lp_reproject_nn(ctypes.byref(sg), fake, ctypes.byref(dg), None, 0, None) == lp.LP_E_INVALID
+    for field, bad in [("rows", 0), ("dlat_deg", 0.0), ("dlon_deg", -1.0), ("lat_first_deg", float("nan"))]:
+        s2 = lp.LatLonGrid(10, 10, 40.0, -3.0, 0.01, 0.01)
+        setattr(s2, field, bad)
+        assert ok(s2, dg) == lp.LP_E_INVALID, field
+    for field, bad in [("cols", -3), ("pitch_km", 0.0), ("k0", float("inf")), ("radius_km", 0.0),
+                       ("y_first_km", float("nan"))]:
+        d2 = lp.TMGrid(10, 10, 0.0, 4400.0, 1.0, -3.0, 0.9996, 6367.0)
+        setattr(d2, field, bad)
+        assert ok(sg, d2) == lp.LP_E_INVALID, field
+    big = lp.TMGrid(300000, 10, 0.0, 4400.0, 1.0, -3.0, 0.9996, 6367.0)
+    assert ok(sg, big) == lp.LP_E_SIZE
+
+
+def test_batch_output_rows_errors():
+    lib = lp.raw()
+    b = lp.Batch([(600, 700), (100, 100)], [0, 0], [(101, 101)])
+    for tile, first, count in [(2, 0, 1), (-1, 0, 1), (0, -1, 5), (0, 0, 0), (0, 590, 11), (1, 0, 101)]:
+        assert lib.lp_batch_set_output_rows(b._b, tile, first, count) == lp.LP_E_INVALID
+    assert lib.lp_batch_set_output_rows(b._b, 0, 10, 590) == lp.LP_OK
+
+
+def test_band_kernel_matches_oracle_geometry():
+    from oracle import latlon as olat
+    from paper_1907_02891_amd import latlon
+    radial = lambda d: np.exp(-d / 30.0) / (1.0 + d)
+    for lat in (0.0, 35.5, 61.0, -48.0):
+        a = latlon.band_kernel(radial, lat, 1 / 240, 1 / 240, 20, 33)
+        b = olat.band_kernel(radial, lat, 1 / 240, 1 / 240, 20, 33, 6367.0)
+        np.testing.assert_allclose(a, b, rtol=1e-13)
+    c = latlon.band_centres([0, 10, 30], 50.0, 0.1)
+    np.testing.assert_allclose(c, [50.0 - 0.1 * 4.5, 50.0 - 0.1 * 19.5])

@@ -143,6 +143,9 @@ def main():
                          "matrix cores with FP16 hi+lo / BF16 x3 split operands")
     ap.add_argument("--kernels", default="auto", choices=["auto", "generic"],
                     help="generic: LDS-staged kernels only (no specialised register kernels)")
+    ap.add_argument("--padding", default="config", choices=["config", "window"],
+                    help="config: the workload's padded size; window: the smallest size that still "
+                         "gives the exact input-sized window (n + floor(k/2) per axis)")
     ap.add_argument("--variants", default=None,
                     help="ROWS,COLUMNS: run these specialised variants instead of autotuning")
     args = ap.parse_args()
@@ -171,7 +174,8 @@ def main():
     stream = torch.cuda.current_stream(dev)
 
     t0 = time.perf_counter()
-    plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=(wl.py, wl.px))
+    pad = (wl.py, wl.px) if args.padding == "config" else lp.window_padding(ny, nx, *K.shape)
+    plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=pad)
     mode, dtype, what = PRECISIONS[args.precision]
     plan.set_precision(mode)
     if args.kernels == "generic":
@@ -234,7 +238,8 @@ def main():
         "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": wl.name, "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
+        "config": {"workload": wl.name if args.padding == "config" else f"{wl.name}-window-p{pad[0]}",
+                   "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
                    "padding": [py, px], "pitch_km": wl.pitch_km,
                    "spectrum_form": {1: "real-quadrant", 2: "complex"}[plan.form],
                    "cols_per_group": plan.shape[0], "rows_per_group": plan.shape[1],

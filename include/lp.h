@@ -81,17 +81,22 @@ const char *lp_version(void);
  * The padded size defaults, per axis, to the smallest number 2^a 3^b 5^c that
  * is >= n + k - 1 (the common size of Sec. 2.5), and even along x.
  * Returns NULL on error (sizes <= 0, pitch <= 0 or non-finite: LP_E_INVALID;
- * default padding above LP_MAX_PY / LP_MAX_PX: LP_E_SIZE). */
+ * n + floor(k/2) above LP_MAX_PY / LP_MAX_PX: LP_E_SIZE). */
 lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double pitch_km);
 
 /* Free the plan (host memory only; the bound workspace stays the caller's).
  * NULL is accepted. */
 void lp_plan_destroy(lp_plan *plan);
 
-/* Override the padded size (Sec. 2.5 allows any size >= n + k - 1; the result
- * does not depend on it beyond round-off).  py >= ny+ky-1 and px >= nx+kx-1,
- * both 5-smooth, px even, py <= LP_MAX_PY, px <= LP_MAX_PX (else LP_E_SIZE).
- * Must precede lp_plan_bind (else LP_E_STATE). */
+/* Override the padded size.  Sec. 2.5 pads to n + k - 1, the extent of the
+ * full linear convolution; the input-sized output window (Sec. 3) needs only
+ * n + floor(k/2) per axis: with that length a kernel tap that wraps round
+ * the circular transform always lands in the zero padding, so the window is
+ * unchanged (beyond round-off) for any padding from there up.
+ * py >= ny + floor(ky/2) and px >= nx + floor(kx/2), both 5-smooth, px even,
+ * py <= LP_MAX_PY, px <= LP_MAX_PX (else LP_E_SIZE).  Must precede
+ * lp_plan_bind (else LP_E_STATE).  lp_plan_create's default is the smallest
+ * such size >= n + k - 1, or >= n + floor(k/2) where that exceeds the maximum. */
 int lp_plan_set_padding(lp_plan *plan, int64_t py, int64_t px);
 
 /* Current padded size into *py, *px (host pointers). */

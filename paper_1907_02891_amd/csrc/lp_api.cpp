@@ -317,10 +317,12 @@ int upload_spec_tables(lp_plan *p)
 
 int set_padding(lp_plan *p, int64_t py, int64_t px)
 {
-    if (py < p->ny + p->ky - 1 || px < p->nx + p->kx - 1)
-        return fail(LP_E_SIZE, "padding %lld x %lld smaller than n + k - 1 = %lld x %lld",
-                    (long long)py, (long long)px, (long long)(p->ny + p->ky - 1),
-                    (long long)(p->nx + p->kx - 1));
+    // The input-sized output window needs only n + floor(k/2): a tap that
+    // wraps round the padded length then always lands in the zero padding.
+    if (py < p->ny + p->ky / 2 || px < p->nx + p->kx / 2)
+        return fail(LP_E_SIZE, "padding %lld x %lld smaller than n + floor(k/2) = %lld x %lld",
+                    (long long)py, (long long)px, (long long)(p->ny + p->ky / 2),
+                    (long long)(p->nx + p->kx / 2));
     if (!is_5smooth(py) || !is_5smooth(px))
         return fail(LP_E_SIZE, "padding %lld x %lld is not of the form 2^a 3^b 5^c",
                     (long long)py, (long long)px);
@@ -493,9 +495,9 @@ lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double p
         fail(LP_E_INVALID, "pitch must be positive and finite");
         return nullptr;
     }
-    if (ny + ky - 1 > LP_MAX_PY || nx + kx - 1 > LP_MAX_PX) {
-        fail(LP_E_SIZE, "n + k - 1 = %lld x %lld beyond the maximum %d x %d",
-             (long long)(ny + ky - 1), (long long)(nx + kx - 1), LP_MAX_PY, LP_MAX_PX);
+    if (ny + ky / 2 > LP_MAX_PY || nx + kx / 2 > LP_MAX_PX) {
+        fail(LP_E_SIZE, "n + floor(k/2) = %lld x %lld beyond the maximum %d x %d",
+             (long long)(ny + ky / 2), (long long)(nx + kx / 2), LP_MAX_PY, LP_MAX_PX);
         return nullptr;
     }
     lp_plan *p = new (std::nothrow) lp_plan();
@@ -504,8 +506,12 @@ lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double p
         return nullptr;
     }
     p->ny = ny; p->nx = nx; p->ky = ky; p->kx = kx; p->pitch = pitch_km;
-    const int64_t py = next_5smooth(ny + ky - 1, false);
-    const int64_t px = next_5smooth(nx + kx - 1, true);
+    // default: the full linear extent n + k - 1 of Sec. 2.5; where that
+    // exceeds the maximum, the input-sized window's n + floor(k/2)
+    int64_t py = next_5smooth(ny + ky - 1, false);
+    int64_t px = next_5smooth(nx + kx - 1, true);
+    if (py > LP_MAX_PY) py = next_5smooth(ny + ky / 2, false);
+    if (px > LP_MAX_PX) px = next_5smooth(nx + kx / 2, true);
     if (set_padding(p, py, px) != LP_OK) {
         delete p;
         return nullptr;

@@ -100,6 +100,8 @@ constexpr ColSpec kColSpecs[] = {
     {5400, 360, 20, 15, 18, 4},
     {5400, 360, 15, 18, 20, 5},
     {5400, 225, 24, 25, 9, 0},
+    {4800, 320, 16, 15, 20, 5},
+    {4800, 320, 20, 15, 16, 5},
     {18432, 768, 32, 24, 24, 0},
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},
@@ -171,6 +173,8 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 4, 2, 0},
     {2700, 128, 15, 15, 12, 6, 2, 1},
     {2700, 96, 12, 15, 15, 4, 2, 1},
+    {2400, 160, 15, 16, 10, 2, 4, 1},
+    {2400, 160, 16, 15, 10, 2, 4, 1},
     {9216, 384, 16, 24, 24, 1, 2, 1},
     {9216, 384, 16, 24, 24, 2, 2, 1},
     {9216, 384, 16, 24, 24, 2, 2, 0},

@@ -469,6 +469,25 @@ def reproject_nn(src, src_grid, dst_grid, *, ground_area=False, out=None, stream
     return out
 
 
+def next_5smooth(n, even=False):
+    """Smallest 2^a 3^b 5^c >= n (even if asked)."""
+    m = max(1, int(n))
+    while True:
+        r = m
+        for f in (2, 3, 5):
+            while r % f == 0:
+                r //= f
+        if r == 1 and (not even or m % 2 == 0):
+            return m
+        m += 1
+
+
+def window_padding(ny, nx, ky, kx):
+    """Smallest padded size that still gives the exact input-sized window:
+    5-smooth, >= n + floor(k/2) per axis, even along x (lp_plan_set_padding)."""
+    return next_5smooth(ny + ky // 2), next_5smooth(nx + kx // 2, even=True)
+
+
 def make_plan(psf, ny, nx, *, pitch_km=0.5, padding=None, device=None, kernels=KERNELS_AUTO,
               precision=PRECISION_FP32):
     """Plan + workspace + kernel spectrum in one call."""

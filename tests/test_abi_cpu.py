@@ -258,3 +258,26 @@ def test_band_kernel_matches_oracle_geometry():
         np.testing.assert_allclose(a, b, rtol=1e-13)
     c = latlon.band_centres([0, 10, 30], 50.0, 0.1)
     np.testing.assert_allclose(c, [50.0 - 0.1 * 4.5, 50.0 - 0.1 * 19.5])
+
+
+def test_window_padding_bounds():
+    """Padding may go down to n + floor(k/2) (the input-sized window), no lower."""
+    p = lp.Plan(4096, 4096, 1201, 1201)
+    assert p.padding == (5400, 5400)
+    assert lp.window_padding(4096, 4096, 1201, 1201) == (4800, 4800)
+    p.set_padding(4800, 4800)
+    assert p.padding == (4800, 4800)
+    q = lp.Plan(250, 250, 101, 101)
+    q.set_padding(300, 300)  # exactly n + floor(k/2)
+    for bad in [(288, 300), (300, 288)]:  # 5-smooth but below the bound
+        with pytest.raises(lp.LPError) as ei:
+            q.set_padding(*bad)
+        assert ei.value.code == lp.LP_E_SIZE
+    e = lp.Plan(100, 120, 20, 31)
+    assert lp.window_padding(100, 120, 20, 31) == (120, 144)
+    e.set_padding(120, 144)
+    with pytest.raises(lp.LPError):
+        e.set_padding(108, 144)  # 108 < 100 + 10
+    # a map whose n + k - 1 exceeds the maximum still gets a plan
+    big = lp.Plan(19000, 100, 2001, 3)
+    assert big.padding[0] >= 19000 + 1000 and big.padding[0] <= lp.MAX_PY

@@ -297,3 +297,36 @@ def test_autotune_picks_a_variant(lp, torch, tmp_path, monkeypatch):
     assert_parity(plan.convolve(x).cpu().numpy(), oracle.conv_same(R, K), label="tuned small")
     rep2 = tune.autotune(plan, x, reps=3, warmup=1)
     assert rep2["rows"]["variant"] == rep["rows"]["variant"]
+
+
+# ----------------------------------------------- input-sized window padding --
+
+WINDOW_CASES = [  # ny, nx, ky, kx, padding (>= n + floor(k/2), 5-smooth, px even), kernels
+    (250, 250, 101, 101, (300, 300), "auto"),      # exactly n + floor(k/2)
+    (256, 256, 101, 101, (320, 320), "auto"),
+    (100, 120, 20, 31, (120, 144), "auto"),        # even kernel rows
+    (4096, 16, 1201, 3, (4800, 18), "auto"),       # specialised 4800-point columns
+    (9, 4096, 3, 1201, (12, 4800), "auto"),        # specialised 2400-point rows
+    (4096, 16, 1201, 3, (4800, 18), "generic"),
+]
+
+
+@pytest.mark.parametrize("case", WINDOW_CASES, ids=[f"{c[0]}x{c[1]}p{c[4][0]}x{c[4][1]}{c[5][0]}" for c in WINDOW_CASES])
+def test_window_padding_full_field(lp, torch, case):
+    """Padding below n + k - 1 but >= n + floor(k/2): the input-sized window
+    is unchanged (a wrapped tap lands in the zero padding)."""
+    ny, nx, ky, kx, pad, kern = case
+    rng = np.random.default_rng(ny + 3 * nx + ky)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = rng.random((ky, kx))
+    plan = lp.make_plan(K, ny, nx, padding=pad,
+                        kernels=lp.KERNELS_GENERIC if kern == "generic" else lp.KERNELS_AUTO)
+    assert plan.padding == pad
+    if kern == "auto" and pad[0] == 4800:
+        assert plan.kernels == lp.KERNELS_SPECIALISED
+    x = torch.from_numpy(R).cuda()
+    S = plan.convolve(x).cpu().numpy()
+    assert_parity(S, oracle.conv_same(R, K), label=f"window {case}")
+    G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
+    A = plan.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    assert_parity(A, oracle.adjoint_same(G, K), label=f"window adjoint {case}")

@@ -330,3 +330,26 @@ def test_window_padding_full_field(lp, torch, case):
     G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
     A = plan.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
     assert_parity(A, oracle.adjoint_same(G, K), label=f"window adjoint {case}")
+
+
+# ---------------------------------------------------------- maximum sizes --
+
+MAX_CASES = [  # ny, nx, ky, kx, padding: the longest column and the longest row a plan accepts
+    (19000, 4, 1481, 3, (20480, 6)),     # Py = LP_MAX_PY: one column fills the 160 KB of LDS
+    (3, 39000, 3, 1501, (4, 40500)),     # Px = 40500: largest even 5-smooth length <= LP_MAX_PX
+    (19500, 4, 1481, 3, None),           # n + k - 1 > LP_MAX_PY: default falls back to n + floor(k/2)
+]
+
+
+@pytest.mark.parametrize("case", MAX_CASES, ids=["py20480", "px40500", "py-default"])
+def test_maximum_sizes_full_field(lp, torch, case):
+    ny, nx, ky, kx, pad = case
+    rng = np.random.default_rng(ny + nx)
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = rng.random((ky, kx))
+    plan = lp.make_plan(K, ny, nx, padding=pad)
+    if pad is not None:
+        assert plan.padding == pad
+    assert plan.padding[0] <= lp.MAX_PY and plan.padding[1] <= lp.MAX_PX
+    y = plan.convolve(torch.from_numpy(R).cuda()).cpu().numpy()
+    assert_parity(y, oracle.conv_same(R, K), label=f"max size {case} P={plan.padding}")

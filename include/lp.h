@@ -284,7 +284,8 @@ int lp_reproject_nn(const lp_latlon_grid *src_grid, const float *src, const lp_t
  * the factorable-classes case of Sec. 2.2 (Eq. 4), handled map by map.  Map t
  * has ny[t] x nx[t] pixels and uses kernel psf_id[t] (0 <= psf_id < n_psf,
  * kernel p of ky[p] x kx[p]).  Each map gets the smallest padded size on each
- * axis, >= n + k - 1, for which the library has specialised kernels; maps
+ * axis, >= n + floor(k/2) (the bound for the input-sized window, see
+ * lp_plan_set_padding), for which the library has specialised kernels; maps
  * sharing a padded size form a class, and maps of a class sharing a kernel
  * share one stored spectrum.  All host arrays are read during the call only.
  * Returns NULL on error: LP_E_INVALID (bad sizes, ids, pitch), LP_E_SIZE (no

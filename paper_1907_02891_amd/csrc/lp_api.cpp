@@ -1134,7 +1134,8 @@ lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *
             delete b;
             return nullptr;
         }
-        const int64_t need_y = ny[t] + ky[psf_id[t]] - 1, need_x = nx[t] + kx[psf_id[t]] - 1;
+        // the input-sized window needs n + floor(k/2) per axis (lp_plan_set_padding)
+        const int64_t need_y = ny[t] + ky[psf_id[t]] / 2, need_x = nx[t] + kx[psf_id[t]] / 2;
         auto py = std::lower_bound(ly.begin(), ly.end(), need_y);
         auto px = std::lower_bound(lx.begin(), lx.end(), need_x);
         if (py == ly.end() || px == lx.end()) {

@@ -106,6 +106,10 @@ constexpr ColSpec kColSpecs[] = {
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},
     {512, 64, 8, 8, 8, 0},
+    {1200, 120, 12, 10, 10, 0},
+    {1440, 144, 12, 12, 10, 0},
+    {1600, 160, 16, 10, 10, 0},
+    {1920, 192, 12, 16, 10, 0},
     {1800, 180, 12, 10, 15, 0},
     {2048, 256, 16, 16, 8, 0},
     {2160, 180, 12, 12, 15, 0},
@@ -183,6 +187,10 @@ constexpr RowSpec kRowSpecs[] = {
     {1440, 128, 12, 12, 10, 2, 3, 0},
     {256, 64, 8, 8, 4, 4, 6, 1},
     {256, 64, 8, 8, 4, 4, 4, 0},
+    {600, 64, 12, 10, 5, 2, 0, 1},
+    {720, 96, 8, 9, 10, 2, 0, 1},
+    {800, 100, 8, 10, 10, 2, 0, 1},
+    {960, 120, 8, 12, 10, 2, 0, 1},
     {900, 100, 10, 9, 10, 2, 0, 1},
     {1024, 128, 8, 8, 16, 2, 0, 1},
     {1080, 120, 9, 10, 12, 2, 0, 1},

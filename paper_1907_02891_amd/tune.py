@@ -159,7 +159,7 @@ def autotune_batch(shapes, psf_ids, psfs, maps, *, pitch_km=0.5, reps=3, warmup=
     ly_all, lx_all = lp.spec_lengths()
     ky = [p.shape[0] for p in psfs]
     kx = [p.shape[1] for p in psfs]
-    need = [(s[0] + ky[i] - 1, s[1] + kx[i] - 1) for s, i in zip(shapes, psf_ids)]
+    need = [(s[0] + ky[i] // 2, s[1] + kx[i] // 2) for s, i in zip(shapes, psf_ids)]
     sets_y = length_sets(min(n[0] for n in need), max(n[0] for n in need), ly_all)
     sets_x = length_sets(min(n[1] for n in need), max(n[1] for n in need), lx_all)
     ys = [torch.empty_like(m) for m in maps]

@@ -143,7 +143,7 @@ def test_shape_choice_fits_lds():
 
 def test_batch_contract_errors():
     with pytest.raises(lp.LPError) as ei:
-        lp.Batch([(100, 100)], [0], [(30000, 3)])
+        lp.Batch([(100, 100)], [0], [(40000, 3)])  # 100 + 20000 beyond the longest specialised column
     assert ei.value.code == lp.LP_E_SIZE
     with pytest.raises(lp.LPError) as ei:
         lp.Batch([(100, 100)], [2], [(5, 5)])

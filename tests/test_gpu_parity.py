@@ -259,6 +259,10 @@ VARIANT_CASES = [  # ny, nx, ky, kx, padding, symmetric
     (37, 4093, 5, 401, (48, 5400), True), (4096, 9, 1201, 3, (5400, 12), False),
     (11, 2049, 3, 801, (16, 2880), False), (2700, 7, 101, 3, (2880, 10), True),
     (29, 255, 9, 3, (40, 512), False), (400, 15, 31, 1, (512, 16), True),
+    (1000, 11, 201, 3, (1200, 12), True), (7, 1000, 3, 201, (8, 1200), False),
+    (1300, 5, 141, 1, (1440, 6), False), (9, 1300, 3, 141, (10, 1440), True),
+    (1500, 6, 101, 3, (1600, 8), True), (5, 1500, 1, 101, (6, 1600), False),
+    (1800, 3, 121, 1, (1920, 4), False), (3, 1800, 1, 121, (4, 1920), True),
 ]
 
 

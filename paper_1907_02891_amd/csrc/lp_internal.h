@@ -173,6 +173,8 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 192, 15, 15, 12, 2, 3, 0},
     {2700, 192, 15, 15, 12, 1, 3, 0},
     {2700, 128, 15, 15, 12, 2, 3, 0},
+    {2700, 180, 20, 15, 9, 2, 0, 1},
+    {2700, 180, 18, 15, 10, 2, 0, 1},
     {2700, 128, 15, 15, 12, 4, 2, 1},
     {2700, 128, 15, 15, 12, 4, 2, 0},
     {2700, 128, 15, 15, 12, 6, 2, 1},

@@ -147,7 +147,7 @@ def main():
                     help="config: the workload's padded size; window: the smallest size that still "
                          "gives the exact input-sized window (n + floor(k/2) per axis)")
     ap.add_argument("--variants", default=None,
-                    help="ROWS,COLUMNS: run these specialised variants instead of autotuning")
+                    help="ROWS,COLUMNS[,ROWS_INVERSE]: run these specialised variants instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -192,7 +192,7 @@ def main():
     t0 = time.perf_counter()
     tuning = None
     if args.variants:
-        for st, k in zip((lp.STAGE_ROWS, lp.STAGE_COLUMNS), args.variants.split(",")):
+        for st, k in zip((lp.STAGE_ROWS, lp.STAGE_COLUMNS, lp.STAGE_ROWS_INVERSE), args.variants.split(",")):
             if plan.variant_count(st) > 0:
                 plan.set_variant(st, int(k))
     elif not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
@@ -230,6 +230,15 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}
 
+    variants = {}
+    if plan.kernels == lp.KERNELS_SPECIALISED:
+        for name, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS), ("rows_inverse", lp.STAGE_ROWS_INVERSE)):
+            if plan.variant_count(st) > 0:
+                t = (tuning or {}).get("rows" if st != lp.STAGE_COLUMNS else "columns", {})
+                tried = {lp.STAGE_ROWS: t.get("forward_ms", t.get("all", [])), lp.STAGE_COLUMNS: t.get("all", []),
+                         lp.STAGE_ROWS_INVERSE: t.get("inverse_ms", [])}[st]
+                variants[name] = {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
+                                  "tried_ms": [round(x, 5) for x in tried]}
     out = {
         "metric": f"output pixels/s per MI355X ({what}) at rel-L2 <= 1e-5",
         "value": ny * nx / (ms_step * 1e-3),
@@ -254,10 +263,7 @@ def main():
                  "wall_s": round(wall, 4)},
         "setup_s": {"inputs": round(t_gen, 2), "plan_bind": round(t_plan, 3),
                     "kernel_spectrum": round(t_spec, 3), "autotune": round(t_tune, 3)},
-        "variants": {lp_stage: {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
-                                "tried_ms": [round(t, 5) for t in (tuning or {}).get(lp_stage, {}).get("all", [])]}
-                     for lp_stage, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS))
-                     if plan.variant_count(st) > 0 and plan.kernels == lp.KERNELS_SPECIALISED},
+        "variants": variants,
         "kernel_source": src_hash,
     }
 

@@ -212,8 +212,11 @@ int lp_plan_kernels(const lp_plan *plan);
  * re-uploads the stage's twiddle tables and synchronises the stream).
  * lp_plan_variant_info writes up to n of {R0, R1, R2, threads per transform,
  * transforms per workgroup, min waves per SIMD, tiles per workgroup (0: a
- * persistent loop; always 1 for the column stage), length}. */
-enum { LP_STAGE_ROWS = 0, LP_STAGE_COLUMNS = 1 };
+ * persistent loop; always 1 for the column stage), length}.
+ * LP_STAGE_ROWS selects the variant of both row stages (and reports the
+ * forward one); LP_STAGE_ROWS_INVERSE the inverse row stage alone, so the
+ * two directions may run different specialisations of the same length. */
+enum { LP_STAGE_ROWS = 0, LP_STAGE_COLUMNS = 1, LP_STAGE_ROWS_INVERSE = 2 };
 int lp_plan_variant_count(const lp_plan *plan, int stage);
 int lp_plan_get_variant(const lp_plan *plan, int stage);
 int lp_plan_set_variant(lp_plan *plan, int stage, int k);

@@ -210,6 +210,7 @@ struct lp_plan {
     // register-resident column stage (if the padded column length has one)
     int col_spec = -1;
     int col_variant = 0, row_variant = 0;  // k-th specialisation of each length
+    int row_variant_inv = 0;               // the inverse row stage's (may differ)
     size_t twc_max = 2, twr_max = 2;       // table floats reserved (largest variant)
     int variant = 0;  // 0: specialised kernels where available, 1: generic only
     int precision = LP_PRECISION_FP32;  // split forms run the generic kernels
@@ -218,7 +219,7 @@ struct lp_plan {
     std::vector<float> twc;  // its four pass tables, concatenated
     size_t twc_off[4] = {0, 0, 0, 0};  // float2 offsets of the four tables
     // register-resident row stages (if the half row length has one)
-    int row_spec = -1;
+    int row_spec = -1, row_spec_inv = -1;  // forward, inverse
     std::vector<float> twr;
     size_t twr_off[4] = {0, 0, 0, 0};
     // workspace layout (byte offsets)
@@ -292,11 +293,23 @@ void build_spec_tables(lp_plan *p)
         const lp::ColSpec c = lp::kColSpecs[p->col_spec];
         spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
     }
+    // forward tables from the forward row variant, inverse ones from the
+    // inverse variant, concatenated
     p->row_spec = lp::row_spec_index(static_cast<int>(p->m), p->row_variant);
+    p->row_spec_inv = lp::row_spec_index(static_cast<int>(p->m), p->row_variant_inv);
     p->twr.clear();
-    if (p->row_spec >= 0) {
-        const lp::RowSpec c = lp::kRowSpecs[p->row_spec];
-        spec_tables(c.r0, c.r1, c.r2, &p->twr, p->twr_off);
+    if (p->row_spec >= 0 && p->row_spec_inv >= 0) {
+        const lp::RowSpec f = lp::kRowSpecs[p->row_spec], i = lp::kRowSpecs[p->row_spec_inv];
+        size_t off_f[4], off_i[4];
+        std::vector<float> ti;
+        spec_tables(f.r0, f.r1, f.r2, &p->twr, off_f);
+        spec_tables(i.r0, i.r1, i.r2, &ti, off_i);
+        const size_t base = p->twr.size() / 2;
+        p->twr.insert(p->twr.end(), ti.begin(), ti.end());
+        p->twr_off[0] = off_f[0];
+        p->twr_off[1] = off_f[1];
+        p->twr_off[2] = base + off_i[2];
+        p->twr_off[3] = base + off_i[3];
     }
 }
 
@@ -338,6 +351,7 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     make_fft(p->py, &p->fy, &p->twy, p->precision);
     p->col_variant = 0;
     p->row_variant = 0;
+    p->row_variant_inv = 0;
     p->twc_max = p->twr_max = 2;
     for (int k = 0; k < lp::col_spec_count(static_cast<int>(py)); ++k) {
         const lp::ColSpec c = lp::kColSpecs[lp::col_spec_index(static_cast<int>(py), k)];
@@ -345,7 +359,7 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     }
     for (int k = 0; k < lp::row_spec_count(static_cast<int>(p->m)); ++k) {
         const lp::RowSpec c = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(p->m), k)];
-        p->twr_max = std::max<size_t>(p->twr_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
+        p->twr_max = std::max<size_t>(p->twr_max, 4 * spec_table_len(c.r0, c.r1, c.r2));  // two variants' tables
     }
     build_spec_tables(p);
     p->rtw.assign(2 * (p->m + 1), 0.f);
@@ -418,7 +432,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     lp::ColArgs ca = col_args(p);
     ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
     const bool spec_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
-    const bool rspec = p->row_spec >= 0 && spec_ok;
+    const bool rspec = p->row_spec >= 0 && p->row_spec_inv >= 0 && spec_ok;
     lp::RowRegArgs rr{};
     if (rspec) {
         const float2 *twr = reinterpret_cast<const float2 *>(p->ws + p->off_twr);
@@ -463,7 +477,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
             return fail_hip(e, "column stage launch");
     }
     if (rec && (e = hipEventRecord(ev[2], p->stream)) != hipSuccess) return fail_hip(e, who);
-    e = rspec ? lp::launch_rows_c2r_reg(W, out, rr, p->row_spec, p->stream)
+    e = rspec ? lp::launch_rows_c2r_reg(W, out, rr, p->row_spec_inv, p->stream)
               : lp::launch_rows_c2r(W, out, ra, p->t_rows, p->stream);
     if (e != hipSuccess) return fail_hip(e, "rows inverse launch");
     if (rec) {
@@ -581,7 +595,7 @@ int lp_plan_kernels(const lp_plan *p)
 int lp_plan_variant_count(const lp_plan *p, int stage)
 {
     if (!p) return 0;
-    if (stage == LP_STAGE_ROWS) return lp::row_spec_count(static_cast<int>(p->m));
+    if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) return lp::row_spec_count(static_cast<int>(p->m));
     if (stage == LP_STAGE_COLUMNS) return lp::col_spec_count(static_cast<int>(p->py));
     return 0;
 }
@@ -589,18 +603,28 @@ int lp_plan_variant_count(const lp_plan *p, int stage)
 int lp_plan_get_variant(const lp_plan *p, int stage)
 {
     if (!p) return -1;
-    return stage == LP_STAGE_ROWS ? p->row_variant : stage == LP_STAGE_COLUMNS ? p->col_variant : -1;
+    switch (stage) {
+        case LP_STAGE_ROWS: return p->row_variant;
+        case LP_STAGE_COLUMNS: return p->col_variant;
+        case LP_STAGE_ROWS_INVERSE: return p->row_variant_inv;
+        default: return -1;
+    }
 }
 
 int lp_plan_set_variant(lp_plan *p, int stage, int k)
 {
     clear_error();
     if (!p) return fail(LP_E_INVALID, "null plan");
-    if (stage != LP_STAGE_ROWS && stage != LP_STAGE_COLUMNS)
+    if (stage != LP_STAGE_ROWS && stage != LP_STAGE_COLUMNS && stage != LP_STAGE_ROWS_INVERSE)
         return fail(LP_E_INVALID, "unknown stage %d", stage);
     const int n = lp_plan_variant_count(p, stage);
     if (k < 0 || k >= n) return fail(LP_E_INVALID, "variant %d out of range [0, %d)", k, n);
-    (stage == LP_STAGE_ROWS ? p->row_variant : p->col_variant) = k;
+    if (stage == LP_STAGE_COLUMNS) {
+        p->col_variant = k;
+    } else {
+        p->row_variant_inv = k;  // LP_STAGE_ROWS sets both directions
+        if (stage == LP_STAGE_ROWS) p->row_variant = k;
+    }
     build_spec_tables(p);
     return p->bound ? upload_spec_tables(p) : LP_OK;
 }
@@ -610,7 +634,7 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
     clear_error();
     if (!p || !info) return fail(LP_E_INVALID, "null argument");
     int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (stage == LP_STAGE_ROWS) {
+    if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
         const int i = lp::row_spec_index(static_cast<int>(p->m), k);
         if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
         const lp::RowSpec c = lp::kRowSpecs[i];

@@ -186,6 +186,7 @@ constexpr RowSpec kRowSpecs[] = {
     {9216, 384, 24, 24, 16, 2, 0, 1},
     {9216, 384, 24, 24, 16, 1, 0, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
+    {1440, 120, 15, 12, 8, 2, 0, 1},
     {1440, 128, 12, 12, 10, 2, 3, 0},
     {256, 64, 8, 8, 4, 4, 6, 1},
     {256, 64, 8, 8, 4, 4, 4, 0},

@@ -26,7 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 LP_OK, LP_E_INVALID, LP_E_SIZE, LP_E_STATE, LP_E_NOMEM, LP_E_DEVICE = 0, -1, -2, -3, -4, -5
 FORM_NONE, FORM_REAL_QUADRANT, FORM_COMPLEX = 0, 1, 2
 KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
-STAGE_ROWS, STAGE_COLUMNS = 0, 1
+STAGE_ROWS, STAGE_COLUMNS, STAGE_ROWS_INVERSE = 0, 1, 2
 PRECISION_FP32, PRECISION_SPLIT_FP16, PRECISION_SPLIT_BF16 = 0, 1, 2
 MAX_CLASSES = 16
 MAX_PY, MAX_PX = 20480, 40958

@@ -51,7 +51,8 @@ def _save_cache(c):
         pass
 
 
-def _stage_time(plan, x, out, stage, reps, warmup, adjoint=False):
+def _stage_times(plan, x, out, reps, warmup, adjoint=False):
+    """Mean ms per call of (rows forward, columns, rows inverse)."""
     if plan.classes > 1:  # x: one map per class
         def run():
             plan.convolve_classes(x, out=out)
@@ -67,9 +68,7 @@ def _stage_time(plan, x, out, stage, reps, warmup, adjoint=False):
         run()
     ms, calls = plan.stage_ms()
     plan.timing(False)
-    if stage == lp.STAGE_ROWS:
-        return (ms[0] + ms[2]) / calls
-    return ms[1] / calls
+    return [m / calls for m in ms]
 
 
 def autotune(plan, x=None, out=None, *, reps=20, warmup=3, use_cache=True, verbose=False):
@@ -96,18 +95,37 @@ def autotune(plan, x=None, out=None, *, reps=20, warmup=3, use_cache=True, verbo
         if cached is not None and 0 <= cached < n:
             plan.set_variant(stage, cached)
             report[name] = {"variant": cached, "ms": None, "all": [], "cached": True}
+            ci = cache.get(key, {}).get(name + "_inverse")
+            if stage == lp.STAGE_ROWS and ci is not None and 0 <= ci < n:
+                plan.set_variant(lp.STAGE_ROWS_INVERSE, ci)
+                report[name]["variant_inverse"] = ci
             continue
-        times = []
+        times, fwd, inv = [], [], []
         for k in range(n):
             plan.set_variant(stage, k)
-            t = _stage_time(plan, x, out, stage, reps, warmup)
-            times.append(t)
+            t = _stage_times(plan, x, out, reps, warmup)
+            if stage == lp.STAGE_ROWS:
+                fwd.append(t[0])
+                inv.append(t[2])
+                times.append(t[0] + t[2])
+            else:
+                times.append(t[1])
             if verbose:
-                print(f"tune {name} variant {k} {plan.variant_info(stage, k)}: {t * 1e3:.1f} us", flush=True)
+                print(f"tune {name} variant {k} {plan.variant_info(stage, k)}: {times[-1] * 1e3:.1f} us", flush=True)
         best = min(range(n), key=lambda k: times[k])
         plan.set_variant(stage, best)
         report[name] = {"variant": best, "ms": times[best], "all": times}
         cache.setdefault(key, {})[name] = best
+        if stage == lp.STAGE_ROWS:
+            # the two row directions are separate kernels: pick each its own
+            bf = min(range(n), key=lambda k: fwd[k])
+            bi = min(range(n), key=lambda k: inv[k])
+            plan.set_variant(lp.STAGE_ROWS, bf)
+            plan.set_variant(lp.STAGE_ROWS_INVERSE, bi)
+            report[name].update({"variant": bf, "variant_inverse": bi, "ms": fwd[bf] + inv[bi],
+                                 "forward_ms": fwd, "inverse_ms": inv})
+            cache[key][name] = bf
+            cache[key][name + "_inverse"] = bi
     if use_cache:
         _save_cache(cache)
     return report

@@ -288,6 +288,14 @@ def test_every_variant(lp, torch, case):
             nvar += 1
         if plan.variant_count(stage):
             plan.set_variant(stage, 0)
+    # the two row directions on different variants (separate twiddle tables)
+    n = plan.variant_count(lp.STAGE_ROWS)
+    for k in range(n if n > 1 else 0):
+        plan.set_variant(lp.STAGE_ROWS, k)
+        plan.set_variant(lp.STAGE_ROWS_INVERSE, (k + 1) % n)
+        assert plan.variant(lp.STAGE_ROWS) == k and plan.variant(lp.STAGE_ROWS_INVERSE) == (k + 1) % n
+        assert_parity(plan.convolve(x).cpu().numpy(), ref, label=f"{case} rows fwd v{k} inv v{(k + 1) % n}")
+        assert_parity(plan.adjoint(x).cpu().numpy(), refa, label=f"adj {case} rows fwd v{k} inv v{(k + 1) % n}")
     assert nvar >= 1
 
 

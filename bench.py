@@ -62,23 +62,25 @@ def model_bytes(ny, nx, py, px, form):
 
 
 def read_pmc(src_hash):
-    """HBM bytes per column-stage dispatch from a committed rocprofv3 --pmc
-    summary, if it was taken on the current kernel sources."""
+    """(HBM bytes, VALU wave-instructions) per column-stage dispatch from a
+    committed rocprofv3 --pmc summary, if it was taken on the current kernel
+    sources (else None for each)."""
     if not os.path.exists(PMC_FILE):
-        return None
+        return None, None
     vals = {}
     for line in open(PMC_FILE):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("source_sha256") != src_hash:
-        return None
+        return None, None
     try:
         f = float(vals["fetch_kib_per_dispatch"]) * float(vals.get("fetch_scale", 1.0))
         w = float(vals["write_kib_per_dispatch"]) * float(vals.get("write_scale", 1.0))
     except (KeyError, ValueError):
-        return None
-    return (f + w) * 1024.0
+        return None, None
+    valu = vals.get("valu_wave_instructions_per_dispatch")
+    return (f + w) * 1024.0, (float(valu) if valu else None)
 
 
 def cpu_leg(oracle_at, n_total, gpu_at, budget_s, unit, what):
@@ -222,13 +224,20 @@ def main():
     py, px = plan.padding
     path_b, cols_b, kh_b = model_bytes(ny, nx, py, px, plan.form)
     src_hash = kernel_source_hash()
-    traffic = read_pmc(src_hash)
+    traffic, valu = read_pmc(src_hash)
     cols_s = stage_avg[1] * 1e-3
     achieved = cols_b / cols_s / 1e9
     col_kernel = "k_cols_reg" if plan.kernels == lp.KERNELS_SPECIALISED else "k_cols_conv"
     roofline = {"bound": "hbm", "kernel": col_kernel, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}
+    if valu is not None:
+        # the unit that binds this kernel: VALU issue (no packed FP32): a wave64
+        # instruction takes its SIMD 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+        issue_peak = 256 * 4 * 2.4e9 / 4.0  # wave-instructions per second
+        rate = valu / cols_s
+        roofline["valu_issue"] = {"wave_instructions": valu, "achieved_per_s": rate,
+                                  "peak_per_s": issue_peak, "frac": round(rate / issue_peak, 4)}
 
     variants = {}
     if plan.kernels == lp.KERNELS_SPECIALISED:

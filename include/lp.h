@@ -334,7 +334,10 @@ int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *co
  * row first at out[tile] + 0: out[tile] then holds count x nx floats.  For
  * overlap-save slabs (a slab convolved with its halo rows, only its own rows
  * kept) with no copy.  Default: all ny rows.  Takes effect at the next
- * lp_convolve_batched.  Errors: LP_E_INVALID (tile or rows out of range). */
+ * lp_convolve_batched.  With windows, out[t] must not overlap any map's
+ * radiance (the classes of a batch run one after another, so a later class
+ * could read rows an earlier one already wrote).  Errors: LP_E_INVALID
+ * (tile or rows out of range). */
 int lp_batch_set_output_rows(lp_batch *batch, int tile, int64_t first, int64_t count);
 
 /* Graph replay (default) or direct launches (enable = 0). */

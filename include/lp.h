@@ -212,7 +212,9 @@ int lp_plan_kernels(const lp_plan *plan);
  * re-uploads the stage's twiddle tables and synchronises the stream).
  * lp_plan_variant_info writes up to n of {R0, R1, R2, threads per transform,
  * transforms per workgroup, min waves per SIMD, tiles per workgroup (0: a
- * persistent loop; always 1 for the column stage), length}.
+ * persistent loop; always 1 for the column stage), length, half exchange
+ * (1: the passes exchange real and imaginary parts through LDS separately,
+ * halving the buffer so that twice as many workgroups fit on a CU)}.
  * LP_STAGE_ROWS selects the variant of both row stages (and reports the
  * forward one); LP_STAGE_ROWS_INVERSE the inverse row stage alone, so the
  * two directions may run different specialisations of the same length. */

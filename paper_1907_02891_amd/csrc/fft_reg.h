@@ -5,7 +5,8 @@
 // compile time from 2/3/4/5/8-point kernels by Cooley-Tukey splitting with
 // constant internal twiddles.  Data stay in registers; LDS is only the
 // exchange buffer between passes (two exchanges per transform), padded by one
-// word in 32 against bank conflicts.  Pass twiddles come from FP32 tables
+// word in 32 against bank conflicts; an exchange may go through it in two
+// halves (real parts, then imaginary parts) to halve its size.  Pass twiddles come from FP32 tables
 // generated in FP64 on the host.
 #pragma once
 
@@ -215,6 +216,7 @@ constexpr int lds_words(int n, int rw) { return rw ? (n / rw) * lds_pitch(rw) : 
 // and 0 otherwise).
 template <int N, int R, int P, int TF, int G, int LIN>
 struct RegPass {
+    static constexpr int RADIX = R;
     static constexpr int NB = N / R;
     static constexpr int S = (NB + TF - 1) / TF;
     static constexpr int LOUT = (P == 1) ? R : 0;
@@ -238,6 +240,40 @@ struct RegPass {
                     const float2 *q = lds + ((i / LIN) * PITCH + i % LIN) * G + g;
 #pragma unroll
                     for (int j = 0; j < R; ++j) v[s][j] = q[j * (NB / LIN) * PITCH * G];
+                }
+            }
+        }
+    }
+
+    // one component (C = 0: real, 1: imaginary) of the inputs, through a
+    // float buffer with the same word layout (exchanges done in two halves):
+    // input j of butterfly i at word in_base(i) + j IN_STRIDE, output j at
+    // out_base(i) + j OUT_STRIDE (times G)
+    static constexpr int IN_STRIDE = (LIN == 0) ? NB : (NB / LIN) * lds_pitch(LIN);
+    static constexpr int OUT_STRIDE = (P == 1) ? 1 : P;
+    __device__ __forceinline__ static int in_base(int i)
+    {
+        if constexpr (LIN == 0) return i;
+        else return (i / LIN) * lds_pitch(LIN) + i % LIN;
+    }
+    __device__ __forceinline__ static int out_base(int i)
+    {
+        if constexpr (P == 1) return i * lds_pitch(R);
+        else return (i - i % P) * R + i % P;
+    }
+
+    template <int C>
+    __device__ __forceinline__ static void load_part(float2 (&v)[S][R], const float *lds, int tt, int g)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tt + s * TF;
+            if (valid(i)) {
+                const float *q = lds + in_base(i) * G + g;
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    if constexpr (C == 0) v[s][j].x = q[j * IN_STRIDE * G];
+                    else v[s][j].y = q[j * IN_STRIDE * G];
                 }
             }
         }
@@ -284,6 +320,20 @@ struct RegPass {
 #pragma unroll
                     for (int j = 0; j < R; ++j) q[j * P * G] = v[s][j];
                 }
+            }
+        }
+    }
+
+    template <int C>
+    __device__ __forceinline__ static void store_part(const float2 (&v)[S][R], float *lds, int tt, int g)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int i = tt + s * TF;
+            if (valid(i)) {
+                float *q = lds + out_base(i) * G + g;
+#pragma unroll
+                for (int j = 0; j < R; ++j) q[j * OUT_STRIDE * G] = (C == 0) ? v[s][j].x : v[s][j].y;
             }
         }
     }

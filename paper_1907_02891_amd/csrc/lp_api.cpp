@@ -633,23 +633,23 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
 {
     clear_error();
     if (!p || !info) return fail(LP_E_INVALID, "null argument");
-    int v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
         const int i = lp::row_spec_index(static_cast<int>(p->m), k);
         if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
         const lp::RowSpec c = lp::kRowSpecs[i];
-        const int t[8] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m};
-        std::copy(t, t + 8, v);
+        const int t[9] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, 0};
+        std::copy(t, t + 9, v);
     } else if (stage == LP_STAGE_COLUMNS) {
         const int i = lp::col_spec_index(static_cast<int>(p->py), k);
         if (i < 0) return fail(LP_E_INVALID, "no column variant %d", k);
         const lp::ColSpec c = lp::kColSpecs[i];
-        const int t[8] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n};
-        std::copy(t, t + 8, v);
+        const int t[9] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half};
+        std::copy(t, t + 9, v);
     } else {
         return fail(LP_E_INVALID, "unknown stage %d", stage);
     }
-    for (int i = 0; i < n && i < 8; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 9; ++i) info[i] = v[i];
     return LP_OK;
 }
 

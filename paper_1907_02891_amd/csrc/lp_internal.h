@@ -90,10 +90,15 @@ namespace lp {
 // Register-resident column stage: padded column length N = R0 * R1 * R2,
 // TF threads per column (one column per workgroup).
 // occ: minimum waves per SIMD asked of the register allocator (0: none).
+// half: the exchanges between passes go through LDS in two halves (real
+// parts, then imaginary parts), which halves the exchange buffer so that
+// twice as many workgroups fit on a CU; occ is then also the most waves per
+// SIMD the allocator plans for (the occupancy the halved buffer allows).
 // Several entries may share a length: they are the variants a plan can pick
 // from (the first is the default; the autotuner measures the others).
 struct ColSpec {
     int n, tf, r0, r1, r2, occ;
+    int half = 0;
 };
 constexpr ColSpec kColSpecs[] = {
     {5400, 360, 20, 18, 15, 5},
@@ -102,6 +107,7 @@ constexpr ColSpec kColSpecs[] = {
     {5400, 225, 24, 25, 9, 0},
     {4800, 320, 16, 15, 20, 5},
     {4800, 320, 20, 15, 16, 5},
+    {18432, 768, 32, 24, 24, 6, 1},
     {18432, 768, 32, 24, 24, 0},
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},

@@ -566,6 +566,166 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     }
 }
 
+// Column kernel with the exchanges in two halves: the same transform,
+// product and layouts as k_cols_reg, but each exchange between passes goes
+// through a float buffer (same word layout) twice, real parts then imaginary
+// parts, so the buffer is half the size and twice as many workgroups fit on
+// a CU (2 per CU for 18432-point columns instead of 1).  Each pass's
+// arithmetic stays in one divergent block; the register allocator plans for
+// exactly OCC waves per SIMD, the occupancy the halved buffer is there to
+// reach.
+template <class A, class B>
+__device__ __forceinline__ void half_mid(const float2 (&x)[A::S][A::RADIX], float2 (&y)[B::S][B::RADIX],
+                                         float *f, int tt, bool act)
+{
+    __syncthreads();
+    if (act) B::template load_part<0>(y, f, tt, 0);
+    __syncthreads();
+    if (act) A::template store_part<1>(x, f, tt, 0);
+    __syncthreads();
+}
+
+template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ, bool SUM>
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64)
+__attribute__((amdgpu_waves_per_eu(SUM ? 0 : OCC, SUM ? 0 : OCC)))
+k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ items)
+{
+    extern __shared__ float2 lds[];
+    float *f = reinterpret_cast<float *>(lds);
+    using F0 = RegPass<N, R0, 1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using I0 = RegPass<N, R2, 1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
+    const int tt = threadIdx.x;
+    const bool act = tt < TF;
+    const int v = xcd_tile(blockIdx.x, gridDim.x);
+    int ny = a.ny;
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        W = it.w;
+        ny = it.ny;
+        a.kh = it.kh;
+    }
+    const int lc = a.lc, cm = (1 << lc) - 1;
+    float2 *col = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
+
+    // Eq. 9: product of the last forward pass's outputs (element u = i + j NB)
+    // with the kernel spectrum
+    auto multiply = [&](float2 (&xl)[F2::S][R2], const void *kh) {
+#pragma unroll
+        for (int s = 0; s < F2::S; ++s) {
+            const int i = tt + s * TF;
+            if (F2::valid(i)) {
+                if constexpr (FORM == 1) {
+                    const float *kq = static_cast<const float *>(kh) +
+                                      ((static_cast<int64_t>(v >> lc) * a.ku) << lc) + (v & cm);
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int u = i + j * F2::NB;
+                        xl[s][j] = cscale(xl[s][j], kq[((2 * u <= N) ? u : N - u) << lc]);
+                    }
+                } else {
+                    const float2 *kc = static_cast<const float2 *>(kh) +
+                                       ((static_cast<int64_t>(v >> lc) * N) << lc) + (v & cm);
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const float2 k = kc[(i + j * F2::NB) << lc];
+                        xl[s][j] = CONJ ? cmulc(xl[s][j], k) : cmul(xl[s][j], k);
+                    }
+                }
+            }
+        }
+    };
+
+    auto forward = [&](const float2 *__restrict__ src, const void *kh, float2 (&xl)[F2::S][R2]) {
+        float2 x0[F0::S][R0];
+        if (act) {
+#pragma unroll
+            for (int s = 0; s < F0::S; ++s) {
+                const int i = tt + s * TF;
+                if (F0::valid(i)) {
+#pragma unroll
+                    for (int j = 0; j < R0; ++j) {
+                        const int n = i + j * F0::NB;
+                        x0[s][j] = (n < ny) ? src[n << lc] : make_float2(0.f, 0.f);
+                    }
+                }
+            }
+            F0::template butterfly<false>(x0, tt);
+            F0::template store_part<0>(x0, f, tt, 0);
+        }
+        float2 x1[F1::S][R1];
+        half_mid<F0, F1>(x0, x1, f, tt, act);
+        if (act) {
+            F1::template load_part<1>(x1, f, tt, 0);
+            F1::template twiddle<false>(x1, a.tw_f1, tt);
+            F1::template butterfly<false>(x1, tt);
+        }
+        __syncthreads();
+        if (act) F1::template store_part<0>(x1, f, tt, 0);
+        half_mid<F1, F2>(x1, xl, f, tt, act);
+        if (act) {
+            F2::template load_part<1>(xl, f, tt, 0);
+            F2::template twiddle<false>(xl, a.tw_f2, tt);
+            F2::template butterfly<false>(xl, tt);
+            multiply(xl, kh);
+        }
+    };
+
+    // the last inverse pass writes rows < ny of the column
+    auto store_out = [&](const float2 (&y)[I2::S][R0]) {
+#pragma unroll
+        for (int s = 0; s < I2::S; ++s) {
+            const int i = tt + s * TF;
+            if (I2::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) {
+                    const int n = i + j * I2::NB;
+                    if (n < ny) col[n << lc] = y[s][j];
+                }
+            }
+        }
+    };
+
+    float2 xl[F2::S][R2];
+    forward(col, a.kh, xl);
+    if constexpr (SUM) {
+        for (int t = 1; t < a.classes; ++t) {
+            float2 z[F2::S][R2];
+            __syncthreads();  // every thread is done reading the exchange buffer
+            forward(col + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
+            if (act) {
+#pragma unroll
+                for (int s = 0; s < F2::S; ++s)
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) xl[s][j] = cadd(xl[s][j], z[s][j]);
+            }
+        }
+    }
+    if (act) I0::template butterfly<true>(xl, tt);
+    __syncthreads();
+    if (act) I0::template store_part<0>(xl, f, tt, 0);
+    float2 y1[I1::S][R1];
+    half_mid<I0, I1>(xl, y1, f, tt, act);
+    if (act) {
+        I1::template load_part<1>(y1, f, tt, 0);
+        I1::template twiddle<true>(y1, a.tw_i1, tt);
+        I1::template butterfly<true>(y1, tt);
+    }
+    __syncthreads();
+    if (act) I1::template store_part<0>(y1, f, tt, 0);
+    float2 y2[I2::S][R0];
+    half_mid<I1, I2>(y1, y2, f, tt, act);
+    if (act) {
+        I2::template load_part<1>(y2, f, tt, 0);
+        I2::template twiddle<true>(y2, a.tw_i2, tt);
+        I2::template butterfly<true>(y2, tt);
+        store_out(y2);
+    }
+}
+
 int col_spec_index(int n, int k)
 {
     for (int i = 0; i < kNumColSpecs; ++i)
@@ -590,14 +750,28 @@ static constexpr int xchg_words(int n, int r0, int r2)
 template <int I>
 static constexpr size_t col_lds_bytes()
 {
-    return static_cast<size_t>(xchg_words(kColSpecs[I].n, kColSpecs[I].r0, kColSpecs[I].r2)) * 8;
+    return static_cast<size_t>(xchg_words(kColSpecs[I].n, kColSpecs[I].r0, kColSpecs[I].r2)) * (kColSpecs[I].half ? 4 : 8);
 }
 
 template <int I, int FORM, bool CONJ, bool SUM = false>
 static const void *col_fn()
 {
     constexpr ColSpec c = kColSpecs[I];
-    return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
+    if constexpr (c.half)
+        return reinterpret_cast<const void *>(&k_cols_half<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
+    else
+        return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
+}
+
+template <int I, int FORM, bool CONJ, bool SUM>
+static void launch_col(dim3 g, dim3 t, size_t lds, hipStream_t s, float2 *W, const ColRegArgs &a,
+                       const BatchItem *items)
+{
+    constexpr ColSpec c = kColSpecs[I];
+    if constexpr (c.half)
+        hipLaunchKernelGGL((k_cols_half<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>), g, t, lds, s, W, a, items);
+    else
+        hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>), g, t, lds, s, W, a, items);
 }
 
 template <int I>
@@ -630,15 +804,15 @@ static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int n
         const size_t lds = col_lds_bytes<I>();
         if (sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
         if (sum && form == 1)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false, true>), g, t, lds, s, W, a, items);
+            launch_col<I, 1, false, true>(g, t, lds, s, W, a, items);
         else if (sum)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false, true>), g, t, lds, s, W, a, items);
+            launch_col<I, 2, false, true>(g, t, lds, s, W, a, items);
         else if (form == 1)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 1, false, false>), g, t, lds, s, W, a, items);
+            launch_col<I, 1, false, false>(g, t, lds, s, W, a, items);
         else if (conj_k)
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, true, false>), g, t, lds, s, W, a, items);
+            launch_col<I, 2, true, false>(g, t, lds, s, W, a, items);
         else
-            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, 2, false, false>), g, t, lds, s, W, a, items);
+            launch_col<I, 2, false, false>(g, t, lds, s, W, a, items);
         return hipGetLastError();
     }
 }

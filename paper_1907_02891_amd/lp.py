@@ -314,11 +314,12 @@ class Plan:
 
     def variant_info(self, stage, k):
         """dict(radices, threads per transform, transforms per workgroup,
-        min waves per SIMD, tiles per workgroup (0: persistent loop), length)."""
-        v = (ctypes.c_int * 8)()
-        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 8))
+        min waves per SIMD, tiles per workgroup (0: persistent loop), length,
+        half exchange)."""
+        v = (ctypes.c_int * 9)()
+        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 9))
         return {"radices": (v[0], v[1], v[2]), "threads": v[3], "per_group": v[4],
-                "min_waves": v[5], "tiles_per_group": v[6], "length": v[7]}
+                "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8])}
 
     def timing(self, enable=True):
         _check(_lib.lp_plan_timing(self._p, int(bool(enable))))

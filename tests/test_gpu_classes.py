@@ -137,3 +137,22 @@ def test_classes_workload_sampled(lp, torch):
     check(y.cpu().numpy().ravel()[idx], oracle.conv_same_classes_pixels(maps, Ks, idx), "classes workload")
     del y, plan
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("case", [(4096, 9, 1201, 3, (5400, 12), True), (17000, 5, 1201, 3, (18432, 8), False)],
+                         ids=["p5400", "p18432"])
+def test_class_sum_every_column_variant(lp, torch, case):
+    """Class-sum column kernels of every compiled column variant."""
+    ny, nx, ky, kx, pad, sym = case
+    rng = np.random.default_rng(ny + nx)
+    T = 3
+    maps = [rng.random((ny, nx)).astype(np.float32) for _ in range(T)]
+    Ks = [sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx)) for _ in range(T)]
+    ref = oracle.conv_same_classes(maps, Ks)
+    plan = lp.make_plan_classes(Ks, ny, nx, padding=pad)
+    xs = [cuda(torch, m) for m in maps]
+    n = plan.variant_count(lp.STAGE_COLUMNS)
+    assert n >= 2
+    for k in range(n):
+        plan.set_variant(lp.STAGE_COLUMNS, k)
+        check(plan.convolve_classes(xs).cpu().numpy(), ref, f"classes {case} column v{k} {plan.variant_info(lp.STAGE_COLUMNS, k)}")

@@ -43,7 +43,21 @@ def workloads():
         "small": (synth.SMALL, synth.small_inputs),
         "adjoint": (synth.ADJOINT, lambda: synth.adjoint_inputs()[:2]),
         "continental": (synth.CONTINENTAL, synth.continental_inputs),
+        "large": (synth.LARGE, synth.large_inputs),
     }
+
+
+def model_bytes_four_step(ny, nx, py, px, form):
+    """As model_bytes, for a plan whose padded columns take the four-step
+    column stage: the outer forward reads the ny stored rows and writes a
+    Py-long scratch column, the middle reads and writes it and reads the
+    spectrum (all Py rows: 4 B real or 8 B complex), the outer inverse reads
+    it and writes the ny rows back."""
+    h = px // 2 + 1
+    kh = (4 if form == 1 else 8) * py * h
+    cols = 8 * h * (2 * ny + 4 * py) + kh
+    path = 4 * ny * nx + 4 * ny * nx + 2 * 8 * ny * h + cols
+    return path, cols, kh
 
 
 def model_bytes(ny, nx, py, px, form):
@@ -133,7 +147,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="country",
-                    choices=["country", "small", "adjoint", "continental", "batched", "classes", "reproject",
+                    choices=["country", "small", "adjoint", "continental", "large", "batched", "classes", "reproject",
                              "bands"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
@@ -222,12 +236,16 @@ def main():
     stage_avg = [s / max(calls, 1) for s in stage_ms]
 
     py, px = plan.padding
-    path_b, cols_b, kh_b = model_bytes(ny, nx, py, px, plan.form)
+    four_step = plan.column_split[0] > 1
+    path_b, cols_b, kh_b = (model_bytes_four_step if four_step else model_bytes)(ny, nx, py, px, plan.form)
     src_hash = kernel_source_hash()
     traffic, valu = read_pmc(src_hash)
     cols_s = stage_avg[1] * 1e-3
     achieved = cols_b / cols_s / 1e9
     col_kernel = "k_cols_reg" if plan.kernels == lp.KERNELS_SPECIALISED else "k_cols_conv"
+    if four_step:
+        col_kernel = "k_long_fwd + k_long_mid + k_long_inv (four-step, P1 x P2 = %d x %d)" % plan.column_split
+        traffic, valu = None, None
     roofline = {"bound": "hbm", "kernel": col_kernel, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}

@@ -59,9 +59,14 @@ typedef enum lp_status {
 /* Spectrum storage forms (lp_plan_spectrum_form). */
 enum { LP_FORM_NONE = 0, LP_FORM_REAL_QUADRANT = 1, LP_FORM_COMPLEX = 2 };
 
-/* Largest padded sizes a plan accepts: a padded column of Py complex FP32
- * values, and half a padded row plus one, must each fit one workgroup's LDS. */
-#define LP_MAX_PY 20480
+/* Largest padded sizes a plan accepts.  Half a padded row plus one must fit
+ * one workgroup's LDS (Px/2 + 1 <= 20480 complex FP32 values).  A padded
+ * column up to 20480 values is transformed within one workgroup; a longer
+ * one (up to LP_MAX_PY) goes through the four-step column stage: Py = P1 P2
+ * with P2 <= 20480, three passes over a Py-long scratch column per stored
+ * column (lp_plan_column_split reports the split).  Four-step plans take one
+ * source class and run their column stage in FP32. */
+#define LP_MAX_PY 131072
 #define LP_MAX_PX 40958
 
 /* Text description of the last failure on this host thread ("" if none).
@@ -227,6 +232,14 @@ int lp_plan_variant_info(const lp_plan *plan, int stage, int k, int *info, int n
 /* Launch shape the plan chose (host pointers, any may be NULL): columns per
  * workgroup of the column stage, rows per workgroup of the row stages. */
 int lp_plan_shape(const lp_plan *plan, int *cols_per_group, int *rows_per_group);
+
+/* Column transform split of the plan: *p1 = 1, *p2 = Py when a padded column
+ * fits one workgroup's LDS; otherwise the four-step factors Py = P1 * P2
+ * (P2 the largest divisor of Py up to 20480: Cooley-Tukey's split of one
+ * length-Py DFT into P2 DFTs of length P1 and P1 of length P2, twiddled by
+ * exp(-2 pi i n2 k1 / Py) between them).  Host pointers; LP_E_INVALID on
+ * NULL. */
+int lp_plan_column_split(const lp_plan *plan, int64_t *p1, int64_t *p2);
 
 /* Arithmetic of the transforms (the DFTs of Eq. 10 inside Eq. 9).
  * LP_PRECISION_FP32 (default): every butterfly on the vector ALU in FP32.

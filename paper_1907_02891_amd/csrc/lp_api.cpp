@@ -204,9 +204,14 @@ struct lp_plan {
     int logc, logb;
     int64_t nblk;
     int t_rows, t_cols;
-    // transforms and tables (host copies)
-    lp::FftDesc fx, fy;
-    std::vector<float> twx, twy, rtw;
+    // transforms and tables (host copies); with four-step columns fy is the
+    // length-P2 transform and f1 the length-P1 one
+    lp::FftDesc fx, fy, f1;
+    std::vector<float> twx, twy, rtw, tw1, twq;
+    // four-step column stage (padded columns longer than one LDS tile)
+    bool long_cols = false;
+    int64_t p1 = 1, p2 = 0;
+    int long_logb = 0, t_outer = 64, t_mid = 64;
     // register-resident column stage (if the padded column length has one)
     int col_spec = -1;
     int col_variant = 0, row_variant = 0;  // k-th specialisation of each length
@@ -224,6 +229,7 @@ struct lp_plan {
     size_t twr_off[4] = {0, 0, 0, 0};
     // workspace layout (byte offsets)
     size_t off_w, off_kh, off_twx, off_twy, off_rtw, off_twc, off_twr, off_mf, bytes;
+    size_t off_t = 0, off_tw1 = 0, off_twq = 0;  // four-step scratch and tables
     size_t scratch_bytes;
     // binding
     char *ws = nullptr;
@@ -259,6 +265,50 @@ void layout(lp_plan *p)
     p->off_twr = p->off_twc + align256(p->twc_max * 4);
     p->off_mf = p->off_twr + align256(p->twr_max * 4);
     p->bytes = p->off_mf + align256(lp::kFragmentBytes);
+    if (p->long_cols) {
+        // Py values per stored column for the four-step scratch, then the
+        // length-P1 twiddles and exp(-2 pi i m / Py)
+        p->off_t = p->bytes;
+        p->off_tw1 = p->off_t + align256(static_cast<size_t>(p->nblk << p->logc) * p->py * 8);
+        p->off_twq = p->off_tw1 + align256(p->tw1.size() * 4);
+        p->bytes = p->off_twq + align256(p->twq.size() * 4);
+    }
+}
+
+// Four-step split of a padded column longer than one LDS tile: P2 the
+// largest divisor of Py within a tile (the fused middle transform), P1 =
+// Py / P2 (the outer transforms, 2^logb of them per workgroup: about 4096
+// values, so that the short outer transforms still fill a workgroup and the
+// reads of consecutive n2 make long runs).
+void plan_long_columns(lp_plan *p)
+{
+    p->long_cols = p->py > lp::kMaxColLen;
+    p->tw1.clear();
+    p->twq.clear();
+    if (!p->long_cols) {
+        p->p1 = 1;
+        p->p2 = 0;
+        return;
+    }
+    int64_t p2 = 1;
+    for (int64_t d = lp::kMaxColLen; d >= 2; --d)
+        if (p->py % d == 0) { p2 = d; break; }
+    p->p2 = p2;
+    p->p1 = p->py / p2;
+    int logb = 0;
+    while ((p->p1 << (logb + 1)) <= 4096 && (int64_t{1} << (logb + 1)) <= p->p2) ++logb;
+    p->long_logb = logb;
+    p->t_outer = threads_for(p->p1 << logb);
+    p->t_mid = threads_for(p->p2);
+    make_fft(p->p1, &p->f1, &p->tw1, 0);
+    make_fft(p->p2, &p->fy, &p->twy, 0);
+    p->twq.resize(2 * p->py);
+    for (int64_t m = 0; m < p->py; ++m) {
+        double c, sn;
+        exp_frac(m, p->py, &c, &sn);
+        p->twq[2 * m] = static_cast<float>(c);
+        p->twq[2 * m + 1] = static_cast<float>(-sn);
+    }
 }
 
 // Launch shape: C = columns per workgroup of the column stage (a power of
@@ -347,8 +397,12 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     p->px = px;
     p->m = px / 2;
     p->h = p->m + 1;
+    if (py > lp::kMaxColLen && p->classes > 1)
+        return fail(LP_E_SIZE, "padded columns of %lld (> %d) take one source class", (long long)py,
+                    lp::kMaxColLen);
     make_fft(p->m, &p->fx, &p->twx, p->precision);
     make_fft(p->py, &p->fy, &p->twy, p->precision);
+    plan_long_columns(p);
     p->col_variant = 0;
     p->row_variant = 0;
     p->row_variant_inv = 0;
@@ -454,7 +508,25 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         if (e != hipSuccess) return fail_hip(e, "rows forward launch");
     }
     if (rec && (e = hipEventRecord(ev[1], p->stream)) != hipSuccess) return fail_hip(e, who);
-    if (p->col_spec >= 0 && spec_ok) {
+    if (p->long_cols) {
+        lp::LongArgs la{};
+        la.ny = static_cast<int32_t>(p->ny);
+        la.py = static_cast<int32_t>(p->py);
+        la.p1 = static_cast<int32_t>(p->p1);
+        la.p2 = static_cast<int32_t>(p->p2);
+        la.lc = p->logc;
+        la.logb = p->long_logb;
+        la.f1 = p->f1;
+        la.f2 = p->fy;
+        la.tw1 = reinterpret_cast<const float2 *>(p->ws + p->off_tw1);
+        la.tw2 = reinterpret_cast<const float2 *>(p->ws + p->off_twy);
+        la.twq = reinterpret_cast<const float2 *>(p->ws + p->off_twq);
+        la.T = reinterpret_cast<float2 *>(p->ws + p->off_t);
+        la.kh = ca.kh;
+        if ((e = lp::launch_long_cols(W, la, static_cast<int>(p->h), p->form, adjoint, p->t_outer, p->t_mid,
+                                      p->stream)) != hipSuccess)
+            return fail_hip(e, "four-step column stage launch");
+    } else if (p->col_spec >= 0 && spec_ok) {
         lp::ColRegArgs cr{};
         const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
         cr.ny = static_cast<int32_t>(p->ny);
@@ -495,7 +567,10 @@ const char *lp_last_error(void) { return g_err.c_str(); }
 
 int lp_last_status(void) { return g_status; }
 
-const char *lp_version(void) { return "lp 0.2 (gfx950, Stockham 2/3/4/5/8 FP32, radix 16 on MFMA split FP16/BF16)"; }
+const char *lp_version(void)
+{
+    return "lp 0.3 (gfx950, Stockham 2/3/4/5/8 FP32, radix 16 on MFMA split FP16/BF16, four-step long columns)";
+}
 
 lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double pitch_km)
 {
@@ -580,6 +655,7 @@ int lp_plan_set_precision(lp_plan *p, int mode)
     // same table sizes (n - 1 twiddles per length), so the layout stands
     make_fft(p->m, &p->fx, &p->twx, mode);
     make_fft(p->py, &p->fy, &p->twy, mode);
+    plan_long_columns(p);  // four-step columns stay FP32
     return LP_OK;
 }
 
@@ -665,6 +741,15 @@ int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
     return LP_OK;
 }
 
+int lp_plan_column_split(const lp_plan *p, int64_t *p1, int64_t *p2)
+{
+    clear_error();
+    if (!p || !p1 || !p2) return fail(LP_E_INVALID, "null argument");
+    *p1 = p->long_cols ? p->p1 : 1;
+    *p2 = p->long_cols ? p->p2 : p->py;
+    return LP_OK;
+}
+
 int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
 {
     clear_error();
@@ -675,7 +760,8 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
         return fail(LP_E_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, p->bytes);
     hipError_t e;
     if (!attributes_set) {
-        if ((e = lp::set_kernel_attributes()) != hipSuccess) return fail_hip(e, "kernel attributes");
+        if ((e = lp::set_kernel_attributes()) != hipSuccess || (e = lp::set_long_attributes()) != hipSuccess)
+            return fail_hip(e, "kernel attributes");
         attributes_set = true;
     }
     p->ws = static_cast<char *>(ws);
@@ -684,7 +770,8 @@ int lp_plan_bind(lp_plan *p, void *ws, size_t bytes, void *stream)
     p->bound = false;
     p->form = LP_FORM_NONE;
     struct { size_t off; const std::vector<float> *v; } up[] = {
-        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy}};
+        {p->off_twx, &p->twx}, {p->off_rtw, &p->rtw}, {p->off_twy, &p->twy},
+        {p->off_tw1, &p->tw1}, {p->off_twq, &p->twq}};
     for (auto &u : up)
         if (!u.v->empty() && (e = hipMemcpyAsync(p->ws + u.off, u.v->data(), u.v->size() * 4, hipMemcpyHostToDevice,
                                 p->stream)) != hipSuccess)
@@ -749,7 +836,8 @@ int kernel_spectra(lp_plan *p, const double *const *psfs, int n, const char *who
         (e = hipMemcpyAsync(dTaby, taby.data(), taby.size() * 8, hipMemcpyHostToDevice, p->stream)) != hipSuccess)
         return fail_hip(e, "kernel upload");
     const int cy = static_cast<int>((ky - 1) / 2), cx = static_cast<int>((kx - 1) / 2);
-    const int ku = static_cast<int>(sym ? p->py / 2 + 1 : p->py);
+    // four-step plans store every row (in the order the middle kernel reads)
+    const int ku = static_cast<int>(sym && !p->long_cols ? p->py / 2 + 1 : p->py);
     const double scale = 1.0 / (static_cast<double>(p->py) * static_cast<double>(p->px));
     for (int t = 0; t < n; ++t) {
         // one kernel at a time through the scratch: the copy of kernel t+1
@@ -763,7 +851,7 @@ int kernel_spectra(lp_plan *p, const double *const *psfs, int n, const char *who
         if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), cy, static_cast<int>(p->py), ku,
                                       static_cast<int>(p->h), p->logc, static_cast<int>(p->nblk), dTaby,
                                       scale, form, p->ws + p->off_kh + static_cast<size_t>(t) * p->kh_class,
-                                      p->stream)) != hipSuccess)
+                                      p->stream, p->long_cols ? static_cast<int>(p->p2) : 0)) != hipSuccess)
             return fail_hip(e, "spectrum columns launch");
         // pageable host source: the copy may return before the transfer is
         // done, so wait before the next kernel overwrites dK
@@ -908,6 +996,9 @@ int lp_plan_set_classes(lp_plan *p, int n)
     if (!p) return fail(LP_E_INVALID, "null plan");
     if (n < 1 || n > LP_MAX_CLASSES) return fail(LP_E_INVALID, "classes %d outside [1, %d]", n, LP_MAX_CLASSES);
     if (p->bound) return fail(LP_E_STATE, "classes must be set before lp_plan_bind");
+    if (n > 1 && p->long_cols)
+        return fail(LP_E_SIZE, "padded columns of %lld (> %d) take one source class", (long long)p->py,
+                    lp::kMaxColLen);
     p->classes = n;
     layout(p);
     return LP_OK;

@@ -78,10 +78,42 @@ hipError_t launch_rows_c2r(const float2 *W, float *S, const RowArgs &a, int thre
                            hipStream_t s);
 hipError_t launch_spec_rows(const double *K, int ky, int kx, int cx, int px, int h,
                             const double2 *tabx, double2 *t1, hipStream_t s);
+// p2 > 0: the spectrum of a four-step plan, stored row r = k1 p2 + k2 holding
+// frequency k1 + (py / p2) k2 (ku must then be py, in both forms).
 hipError_t launch_spec_cols(const double2 *t1, int ky, int cy, int py, int ku, int h,
                             int logc, int nblk, const double2 *taby, double scale,
-                            int form, void *kh, hipStream_t s);
+                            int form, void *kh, hipStream_t s, int p2 = 0);
 hipError_t set_kernel_attributes();
+
+// ------------------------------------------------ four-step column stage --
+// A padded column longer than one LDS tile (Py > kMaxColLen complex values)
+// is transformed as a P1 x P2 matrix: element n = P2 n1 + n2, frequency
+// k = k1 + P1 k2, so that
+//   X[k1 + P1 k2] = sum_n2 w_P2^(n2 k2) w_Py^(n2 k1) sum_n1 x[P2 n1 + n2] w_P1^(n1 k1),
+// and the inverse runs the same steps backwards.  Three kernels:
+//   outer forward   length-P1 DFTs over stride-P2 elements (rows < ny of the
+//                   intermediate), times w_Py^(n2 k1), into the scratch T;
+//   middle          per (column, k1): length-P2 DFT, product with the
+//                   spectrum (Eq. 9), inverse length-P2 DFT, times
+//                   w_Py^(-n2 k1), in place in T;
+//   outer inverse   inverse length-P1 DFTs, rows n < ny back to the
+//                   intermediate.
+constexpr int kMaxColLen = kLdsBytes / 8;  // 20480 complex values
+struct LongArgs {
+    int32_t ny;          // stored rows of the intermediate
+    int32_t py, p1, p2;  // Py = P1 * P2, P2 <= kMaxColLen
+    int32_t lc;          // log2 of the intermediate's column interleave
+    int32_t logb;        // log2 of the transforms per workgroup of the outer kernels
+    FftDesc f1, f2;      // complex transforms of lengths P1 and P2
+    const float2 *tw1, *tw2;
+    const float2 *twq;   // exp(-2 pi i m / Py), 0 <= m < Py
+    float2 *T;           // scratch: column v at T + v Py, element (k1, n2) at k1 P2 + n2
+    const void *kh;      // spectrum (float real form or float2), stored row
+                         // r = k1 P2 + k2 of column v at ((v >> lc) Py + r) << lc | (v & (2^lc - 1))
+};
+hipError_t launch_long_cols(float2 *W, const LongArgs &a, int ncols, int form, bool conj_k,
+                            int threads_outer, int threads_mid, hipStream_t s);
+hipError_t set_long_attributes();
 
 }  // namespace lp
 

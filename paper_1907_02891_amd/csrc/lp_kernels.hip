@@ -19,6 +19,8 @@
 // workgroup of the neighbouring column takes the other half of each line).
 // Real transforms use the half-length trick: z[n] = x[2n] + i x[2n+1] is
 // transformed at length M = Px/2 and split with exp(-2 pi i k/Px).
+#include <algorithm>
+
 #include "fft_lds.h"
 
 namespace lp {
@@ -254,11 +256,14 @@ __global__ void __launch_bounds__(256) k_spec_rows(const double *__restrict__ K,
 __global__ void __launch_bounds__(256) k_spec_cols(const double2 *__restrict__ t1, int ky, int cy,
                                                    int py, int ku, int h, int logc, int nblk,
                                                    const double2 *__restrict__ taby, double scale,
-                                                   int form, void *__restrict__ kh)
+                                                   int form, void *__restrict__ kh, int r0, int p2)
 {
-    const int u = blockIdx.y;
+    // stored row r; frequency u = r, or k1 + (py / p2) k2 for r = k1 p2 + k2
+    // in the four-step order
+    const int r = r0 + static_cast<int>(blockIdx.y);
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= ku || v >= (nblk << logc)) return;
+    if (r >= ku || v >= (nblk << logc)) return;
+    const int u = p2 ? r / p2 + (py / p2) * (r % p2) : r;
     double re = 0.0, im = 0.0;
     if (v < h) {
         int64_t m0 = (-static_cast<int64_t>(u) * cy) % py;
@@ -277,7 +282,7 @@ __global__ void __launch_bounds__(256) k_spec_cols(const double2 *__restrict__ t
         }
     }
     const int vb = v >> logc, c = v & ((1 << logc) - 1);
-    const int64_t idx = ((static_cast<int64_t>(vb) * ku + u) << logc) + c;
+    const int64_t idx = ((static_cast<int64_t>(vb) * ku + r) << logc) + c;
     if (form == 1)
         static_cast<float *>(kh)[idx] = static_cast<float>(re * scale);
     else
@@ -379,13 +384,18 @@ hipError_t launch_spec_rows(const double *K, int ky, int kx, int cx, int px, int
 
 hipError_t launch_spec_cols(const double2 *t1, int ky, int cy, int py, int ku, int h, int logc,
                             int nblk, const double2 *taby, double scale, int form, void *kh,
-                            hipStream_t s)
+                            hipStream_t s, int p2)
 {
     const int ncol = nblk << logc;
-    const dim3 g((ncol + 255) / 256, ku), t(256);
-    hipLaunchKernelGGL(k_spec_cols, g, t, 0, s, t1, ky, cy, py, ku, h, logc, nblk, taby, scale,
-                       form, kh);
-    return hipGetLastError();
+    // grid.y is limited to 65535: stored rows in chunks
+    for (int r0 = 0; r0 < ku; r0 += 65535) {
+        const dim3 g((ncol + 255) / 256, std::min(65535, ku - r0)), t(256);
+        hipLaunchKernelGGL(k_spec_cols, g, t, 0, s, t1, ky, cy, py, ku, h, logc, nblk, taby, scale,
+                           form, kh, r0, p2);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int SPLIT>

@@ -29,7 +29,8 @@ KERNELS_AUTO, KERNELS_GENERIC, KERNELS_SPECIALISED = 0, 1, 2
 STAGE_ROWS, STAGE_COLUMNS, STAGE_ROWS_INVERSE = 0, 1, 2
 PRECISION_FP32, PRECISION_SPLIT_FP16, PRECISION_SPLIT_BF16 = 0, 1, 2
 MAX_CLASSES = 16
-MAX_PY, MAX_PX = 20480, 40958
+MAX_PY, MAX_PX = 131072, 40958
+MAX_COLUMN_TILE = 20480  # longer padded columns take the four-step column stage
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -73,6 +74,7 @@ _SIGS = {
     "lp_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_stage_ms": ([_vp, _dp, ctypes.c_int, _ip], ctypes.c_int),
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
+    "lp_plan_column_split": ([_vp, _i64p, _i64p], ctypes.c_int),
     "lp_plan_set_kernels": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_kernels": ([_vp], ctypes.c_int),
     "lp_plan_set_precision": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -187,6 +189,14 @@ class Plan:
         c, b = ctypes.c_int(), ctypes.c_int()
         _check(_lib.lp_plan_shape(self._p, ctypes.byref(c), ctypes.byref(b)))
         return c.value, b.value
+
+    @property
+    def column_split(self):
+        """(P1, P2): (1, Py) when a padded column fits one workgroup, else the
+        four-step factors Py = P1 * P2."""
+        p1, p2 = ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.lp_plan_column_split(self._p, ctypes.byref(p1), ctypes.byref(p2)))
+        return p1.value, p2.value
 
     def bind(self, device=None, stream=None, workspace=None):
         """Allocate (or take) a torch uint8 device workspace and bind it with

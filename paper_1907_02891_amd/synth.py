@@ -138,10 +138,12 @@ COUNTRY = Workload("country-4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 54
 CONTINENTAL = Workload("continental-16384x16384-psf2001-p18432", 16384, 16384, 2001, 2001,
                        18432, 18432, 0.5, 1002)
 ADJOINT = Workload("adjoint-2048x2048-psf801-p2880", 2048, 2048, 801, 801, 2880, 2880, 0.5, 1004)
+# longer than one LDS tile per column: the four-step column stage
+LARGE = Workload("large-24000x24000-psf2001-p26244", 24000, 24000, 2001, 2001, 26244, 26244, 0.5, 1006)
 BATCHED_SEED = 1003
 CLASSES = Workload("classes-3x4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 5400, 5400, 0.5, 1005)
 
-WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT, CLASSES)}
+WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT, CLASSES, LARGE)}
 
 
 def small_inputs(seed=SMALL.seed):
@@ -167,6 +169,15 @@ def continental_inputs(seed=CONTINENTAL.seed, n=16384):
     kernel d^-2.5 exp(-d/80 km) cut to a 500 km disk."""
     rng = np.random.default_rng(seed)
     R = radiance_map(n, n, 6000, 0.20, (2.0, 40.0), rng)
+    K = psf_powexp(1000, 2.5, 80.0, 0.5, radius_km=500.0)
+    return R, K
+
+
+def large_inputs(seed=LARGE.seed, n=24000):
+    """24000x24000 map at the continental density (20% background, 12875
+    blobs, sigma 2-40 px); the continental 2001x2001 kernel (500 km disk)."""
+    rng = np.random.default_rng(seed)
+    R = radiance_map(n, n, 12875, 0.20, (2.0, 40.0), rng)
     K = psf_powexp(1000, 2.5, 80.0, 0.5, radius_km=500.0)
     return R, K
 

@@ -43,9 +43,46 @@ def test_create_rejects_bad_arguments(args):
     assert ei.value.code == lp.LP_E_INVALID
 
 
-def test_create_rejects_oversize():
+@pytest.mark.parametrize("shape", [(131000, 100, 2001, 3), (100, 40000, 3, 2001)])
+def test_create_rejects_oversize(shape):
     with pytest.raises(lp.LPError) as ei:
-        lp.Plan(20000, 100, 2001, 3)
+        lp.Plan(*shape)
+    assert ei.value.code == lp.LP_E_SIZE
+
+
+def _largest_divisor_within(n, cap):
+    return max(d for d in range(2, cap + 1) if n % d == 0)
+
+
+@pytest.mark.parametrize("shape", [(20000, 4, 1001, 3), (24000, 24000, 2001, 2001), (60000, 10, 3001, 3),
+                                   (75000, 3, 3001, 1), (130000, 2, 1001, 1)])
+def test_four_step_column_split(shape):
+    """Padded columns longer than one LDS tile (20480 values) split as
+    Py = P1 P2 with P2 the largest divisor of Py within a tile."""
+    p = lp.Plan(*shape)
+    py = p.padding[0]
+    assert py > lp.MAX_COLUMN_TILE and py <= lp.MAX_PY
+    p1, p2 = p.column_split
+    assert p1 * p2 == py and p1 >= 2
+    assert p2 == _largest_divisor_within(py, lp.MAX_COLUMN_TILE)
+    # the workspace holds a Py-long scratch column per stored column
+    h = p.padding[1] // 2 + 1
+    assert p.workspace_bytes >= (h + h % 2) * py * 8
+    q = lp.Plan(4096, 4096, 1201, 1201)
+    assert q.column_split == (1, q.padding[0])
+
+
+def test_four_step_takes_one_class():
+    p = lp.Plan(20000, 4, 1001, 3)
+    with pytest.raises(lp.LPError) as ei:
+        p.set_classes(2)
+    assert ei.value.code == lp.LP_E_SIZE
+    p.set_classes(1)
+    q = lp.Plan(19900, 4, 1001, 3)
+    q.set_padding(20480, 6)  # one tile: classes allowed
+    q.set_classes(3)
+    with pytest.raises(lp.LPError) as ei:
+        q.set_padding(20736, 6)
     assert ei.value.code == lp.LP_E_SIZE
 
 
@@ -79,7 +116,7 @@ def test_default_padding_property(n):
 
 @pytest.mark.parametrize("pad,code", [((355, 360), lp.LP_E_SIZE), ((360, 355), lp.LP_E_SIZE),
                                       ((364, 360), lp.LP_E_SIZE), ((360, 375), lp.LP_E_SIZE),
-                                      ((21870, 512), lp.LP_E_SIZE), ((375, 512), None),
+                                      ((131220, 512), lp.LP_E_SIZE), ((21870, 512), None), ((375, 512), None),
                                       ((512, 512), None)])
 def test_set_padding_validation(pad, code):
     p = lp.Plan(256, 256, 101, 101)

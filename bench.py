@@ -147,7 +147,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="country",
-                    choices=["country", "small", "adjoint", "continental", "large", "batched", "classes", "reproject",
+                    choices=["country", "small", "adjoint", "continental", "large", "slab", "batched", "classes", "reproject",
                              "bands"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu", action="store_true")
@@ -180,6 +180,8 @@ def main():
         return bench_reproject(args)
     if args.workload == "bands":
         return bench_bands(args)
+    if args.workload == "slab":
+        return bench_slab(args)
     wl, make_inputs = workloads()[args.workload]
     t0 = time.perf_counter()
     R, K = make_inputs()
@@ -612,6 +614,66 @@ def bench_bands(args):
                                       lambda idx: yh[idx], args.cpu_budget, "output pixels/s",
                                       "output pixels, FP64 direct sums with each row's band kernel")
     print(json.dumps(res), flush=True)
+
+
+def bench_slab(args):
+    """One GPU's share of the continental map (16384 x 16384, 2001 x 2001
+    kernel) under an 8-way split by overlap-save row slabs: output rows
+    [r0, r0 + 2048) from input rows [r0 - 1000, r0 + 3048) (a 4048-row slab
+    with whole halos), so the kept rows need only 4048 padded rows: class
+    4320 x 18432.  Whole-job rate of 8 such GPUs = 8 x this value (weak
+    scaling, no communication when every GPU holds its input rows)."""
+    import torch
+    from paper_1907_02891_amd import lp, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    R, K = synth.continental_inputs()
+    n, k = R.shape[1], K.shape[0]
+    cy = (k - 1) // 2
+    r0, rows = 3 * 2048, 2048
+    slab = np.ascontiguousarray(R[r0 - cy:r0 + rows + cy])
+    del R
+    t0 = time.perf_counter()
+    b = lp.Batch([slab.shape], [0], [K.shape], pitch_km=synth.CONTINENTAL.pitch_km)
+    b.set_output_rows(0, cy, rows)
+    b.bind(device=dev, stream=stream)
+    b.set_kernels([K])
+    t_setup = time.perf_counter() - t0
+    x = torch.from_numpy(slab).to(dev)
+    y = torch.empty((rows, n), dtype=torch.float32, device=dev)
+    ms = _timed(lambda: b.convolve([x], [y]), stream, args.steps, args.warmup)
+    py, px = b.groups[0]["padding"]
+    h = px // 2 + 1
+    path_b = 4 * slab.size + 4 * rows * n + 4 * 8 * slab.shape[0] * h + 4 * (py // 2 + 1) * h
+    res = {
+        "metric": "output pixels/s per MI355X (one GPU's overlap-save slab of the continental map)",
+        "value": rows * n / (ms * 1e-3), "unit": "output pixels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "slab-4048x16384-keep2048-psf2001 (continental, 8-way row split)",
+                   "slab_rows": slab.shape[0], "kept_rows": [cy, cy + rows], "padding": [py, px]},
+        "roofline": {"bound": "hbm", "kernel": "whole step (three passes)", "achieved": round(path_b / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(path_b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes": path_b},
+        "eight_gpu_projection": {"value": 8 * rows * n / (ms * 1e-3), "ms_per_step": round(ms, 5),
+                                 "assumes": "input rows resident on every GPU, no halo exchange"},
+        "setup_s": {"batch_bind_spectrum": round(t_setup, 3)},
+    }
+    if not args.no_cpu:
+        yh = y.cpu().numpy().ravel()
+        Sd = slab.astype(np.float64)
+        # flat index into the kept rows -> the slab's "same" output at row cy + i
+        res["cpu_baseline"] = cpu_leg(lambda idx: oracle_slab(Sd, K, idx, cy, n), rows * n,
+                                      lambda idx: yh[idx], args.cpu_budget, "output pixels/s",
+                                      "kept output pixels, FP64 direct sums over the 2001 x 2001 kernel")
+    print(json.dumps(res), flush=True)
+
+
+def oracle_slab(S, K, idx, cy, n):
+    import oracle
+    return oracle.conv_same_pixels(S, K, np.asarray(idx, np.int64) + cy * n)
 
 
 if __name__ == "__main__":

@@ -351,8 +351,17 @@ int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *co
  * kept) with no copy.  Default: all ny rows.  Takes effect at the next
  * lp_convolve_batched.  With windows, out[t] must not overlap any map's
  * radiance (the classes of a batch run one after another, so a later class
- * could read rows an earlier one already wrote).  Errors: LP_E_INVALID
- * (tile or rows out of range). */
+ * could read rows an earlier one already wrote).
+ * Padding (Sec. 2.5): output row i sums input rows i + cy - a over the
+ * kernel rows a < ky (cy = (ky - 1) / 2), so on a circle of Py rows the
+ * kept rows [k0, k1) stay exact when Py >= max(k1 + cy, ny + ky - 1 - cy
+ * - k0): n + floor(k/2) for the whole map, down to ny for a slab that keeps
+ * only rows whose kernel footprint lies inside it.  Called before the
+ * first lp_batch_bind, the padding classes are chosen again from this
+ * bound (lp_batch_workspace_bytes changes; per-class variants reset);
+ * after it, a window that needs more rows than its map's class has is
+ * refused with LP_E_STATE.  Errors: LP_E_INVALID (tile or rows out of
+ * range), LP_E_SIZE (no specialised length is long enough). */
 int lp_batch_set_output_rows(lp_batch *batch, int tile, int64_t first, int64_t count);
 
 /* Graph replay (default) or direct launches (enable = 0). */

@@ -1077,6 +1077,7 @@ struct lp_batch {
     int n = 0, n_psf = 0;
     std::vector<int64_t> ny, nx, ky, kx;
     std::vector<int64_t> keep0, keep_n;  // output rows [keep0, keep0 + keep_n) of each map
+    std::vector<int64_t> ly, lx;         // padded lengths the classes may use
     std::vector<int> psf;
     double pitch = 0;
     std::vector<Group> groups;
@@ -1177,88 +1178,37 @@ hipError_t batch_launch_all(lp_batch *b, hipStream_t s)
 
 }  // namespace
 
-extern "C" {
-
-lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
-                          const int64_t *ky, const int64_t *kx, double pitch_km)
+// Padded rows a map needs for its output rows [k0, k1) (Sec. 2.5 with the
+// circular wrap-round made harmless): output row i sums x[i + cy - a] over
+// the kernel rows a < ky, with x = 0 outside [0, ny).  On a circle of Py
+// rows the largest index k1 - 1 + cy must stay below Py, and the most
+// negative one, k0 + cy - (ky - 1), must wrap into the zero rows [ny, Py):
+// Py >= max(k1 + cy, ny + ky - 1 - cy - k0).  For the whole map this is
+// n + floor(k/2); for an overlap-save slab that keeps only rows whose
+// kernel footprint lies inside it, it falls to ny.
+static int64_t batch_need_y(const lp_batch *b, int t)
 {
-    return lp_batch_create_padded(n_tiles, ny, nx, psf_id, n_psf, ky, kx, pitch_km, nullptr, 0, nullptr, 0);
+    const int64_t k = b->ky[b->psf[t]], cy = (k - 1) / 2;
+    const int64_t k0 = b->keep0[t], k1 = b->keep0[t] + b->keep_n[t];
+    return std::max(k1 + cy, b->ny[t] + k - 1 - cy - k0);
 }
 
-lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
-                                 const int64_t *ky, const int64_t *kx, double pitch_km, const int64_t *lengths_y,
-                                 int n_ly, const int64_t *lengths_x, int n_lx)
+// Padding classes and workspace layout from the maps, kernels, output rows
+// and allowed lengths.  Host only.
+static int batch_plan(lp_batch *b)
 {
-    clear_error();
-    if (n_tiles <= 0 || n_psf <= 0 || !ny || !nx || !psf_id || !ky || !kx) {
-        fail(LP_E_INVALID, "batch: empty or null arguments");
-        return nullptr;
-    }
-    if (!(pitch_km > 0.0) || !std::isfinite(pitch_km)) {
-        fail(LP_E_INVALID, "pitch must be positive and finite");
-        return nullptr;
-    }
-    for (int p = 0; p < n_psf; ++p)
-        if (ky[p] <= 0 || kx[p] <= 0) {
-            fail(LP_E_INVALID, "kernel %d has a non-positive size", p);
-            return nullptr;
-        }
-    std::vector<int64_t> ly = spec_lengths(true), lx = spec_lengths(false);
-    if (n_ly > 0 || n_lx > 0) {
-        if ((n_ly > 0 && !lengths_y) || (n_lx > 0 && !lengths_x) || n_ly < 0 || n_lx < 0) {
-            fail(LP_E_INVALID, "batch: null or negative length lists");
-            return nullptr;
-        }
-        auto restrict_to = [](std::vector<int64_t> &all, const int64_t *want, int n, const char *axis) {
-            std::vector<int64_t> keep;
-            for (int i = 0; i < n; ++i) {
-                if (std::find(all.begin(), all.end(), want[i]) == all.end()) {
-                    fail(LP_E_SIZE, "batch: %s length %lld has no specialised kernels", axis, (long long)want[i]);
-                    return false;
-                }
-                keep.push_back(want[i]);
-            }
-            std::sort(keep.begin(), keep.end());
-            keep.erase(std::unique(keep.begin(), keep.end()), keep.end());
-            all = keep;
-            return true;
-        };
-        if ((n_ly > 0 && !restrict_to(ly, lengths_y, n_ly, "column")) ||
-            (n_lx > 0 && !restrict_to(lx, lengths_x, n_lx, "row")))
-            return nullptr;
-    }
-    lp_batch *b = new (std::nothrow) lp_batch();
-    if (!b) {
-        fail(LP_E_NOMEM, "out of host memory");
-        return nullptr;
-    }
-    b->n = n_tiles;
-    b->n_psf = n_psf;
-    b->pitch = pitch_km;
-    b->ny.assign(ny, ny + n_tiles);
-    b->keep0.assign(n_tiles, 0);
-    b->keep_n.assign(ny, ny + n_tiles);
-    b->nx.assign(nx, nx + n_tiles);
-    b->psf.assign(psf_id, psf_id + n_tiles);
-    b->ky.assign(ky, ky + n_psf);
-    b->kx.assign(kx, kx + n_psf);
+    const int n_tiles = b->n;
+    const std::vector<int64_t> &ny = b->ny, &nx = b->nx, &ky = b->ky, &kx = b->kx, &ly = b->ly, &lx = b->lx;
+    const std::vector<int> &psf_id = b->psf;
+    b->groups.clear();
     b->item_group.assign(n_tiles, -1);
     for (int t = 0; t < n_tiles; ++t) {
-        if (ny[t] <= 0 || nx[t] <= 0 || psf_id[t] < 0 || psf_id[t] >= n_psf) {
-            fail(LP_E_INVALID, "tile %d: bad size or kernel id", t);
-            delete b;
-            return nullptr;
-        }
-        // the input-sized window needs n + floor(k/2) per axis (lp_plan_set_padding)
-        const int64_t need_y = ny[t] + ky[psf_id[t]] / 2, need_x = nx[t] + kx[psf_id[t]] / 2;
+        const int64_t need_y = batch_need_y(b, t), need_x = nx[t] + kx[psf_id[t]] / 2;
         auto py = std::lower_bound(ly.begin(), ly.end(), need_y);
         auto px = std::lower_bound(lx.begin(), lx.end(), need_x);
-        if (py == ly.end() || px == lx.end()) {
-            fail(LP_E_SIZE, "tile %d (%lld x %lld, kernel %d) needs padding beyond the specialised sizes",
-                 t, (long long)ny[t], (long long)nx[t], psf_id[t]);
-            delete b;
-            return nullptr;
-        }
+        if (py == ly.end() || px == lx.end())
+            return fail(LP_E_SIZE, "tile %d (%lld x %lld, kernel %d) needs padding beyond the specialised sizes",
+                        t, (long long)ny[t], (long long)nx[t], psf_id[t]);
         int gi = -1;
         for (size_t k = 0; k < b->groups.size(); ++k)
             if (b->groups[k].py == *py && b->groups[k].px == *px) gi = static_cast<int>(k);
@@ -1329,6 +1279,86 @@ lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *
         }
     }
     b->bytes = off;
+    return LP_OK;
+}
+
+extern "C" {
+
+lp_batch *lp_batch_create(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
+                          const int64_t *ky, const int64_t *kx, double pitch_km)
+{
+    return lp_batch_create_padded(n_tiles, ny, nx, psf_id, n_psf, ky, kx, pitch_km, nullptr, 0, nullptr, 0);
+}
+
+lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *nx, const int *psf_id, int n_psf,
+                                 const int64_t *ky, const int64_t *kx, double pitch_km, const int64_t *lengths_y,
+                                 int n_ly, const int64_t *lengths_x, int n_lx)
+{
+    clear_error();
+    if (n_tiles <= 0 || n_psf <= 0 || !ny || !nx || !psf_id || !ky || !kx) {
+        fail(LP_E_INVALID, "batch: empty or null arguments");
+        return nullptr;
+    }
+    if (!(pitch_km > 0.0) || !std::isfinite(pitch_km)) {
+        fail(LP_E_INVALID, "pitch must be positive and finite");
+        return nullptr;
+    }
+    for (int p = 0; p < n_psf; ++p)
+        if (ky[p] <= 0 || kx[p] <= 0) {
+            fail(LP_E_INVALID, "kernel %d has a non-positive size", p);
+            return nullptr;
+        }
+    std::vector<int64_t> ly = spec_lengths(true), lx = spec_lengths(false);
+    if (n_ly > 0 || n_lx > 0) {
+        if ((n_ly > 0 && !lengths_y) || (n_lx > 0 && !lengths_x) || n_ly < 0 || n_lx < 0) {
+            fail(LP_E_INVALID, "batch: null or negative length lists");
+            return nullptr;
+        }
+        auto restrict_to = [](std::vector<int64_t> &all, const int64_t *want, int n, const char *axis) {
+            std::vector<int64_t> keep;
+            for (int i = 0; i < n; ++i) {
+                if (std::find(all.begin(), all.end(), want[i]) == all.end()) {
+                    fail(LP_E_SIZE, "batch: %s length %lld has no specialised kernels", axis, (long long)want[i]);
+                    return false;
+                }
+                keep.push_back(want[i]);
+            }
+            std::sort(keep.begin(), keep.end());
+            keep.erase(std::unique(keep.begin(), keep.end()), keep.end());
+            all = keep;
+            return true;
+        };
+        if ((n_ly > 0 && !restrict_to(ly, lengths_y, n_ly, "column")) ||
+            (n_lx > 0 && !restrict_to(lx, lengths_x, n_lx, "row")))
+            return nullptr;
+    }
+    lp_batch *b = new (std::nothrow) lp_batch();
+    if (!b) {
+        fail(LP_E_NOMEM, "out of host memory");
+        return nullptr;
+    }
+    b->n = n_tiles;
+    b->n_psf = n_psf;
+    b->pitch = pitch_km;
+    b->ny.assign(ny, ny + n_tiles);
+    b->keep0.assign(n_tiles, 0);
+    b->keep_n.assign(ny, ny + n_tiles);
+    b->nx.assign(nx, nx + n_tiles);
+    b->psf.assign(psf_id, psf_id + n_tiles);
+    b->ky.assign(ky, ky + n_psf);
+    b->kx.assign(kx, kx + n_psf);
+    b->ly = ly;
+    b->lx = lx;
+    for (int t = 0; t < n_tiles; ++t)
+        if (ny[t] <= 0 || nx[t] <= 0 || psf_id[t] < 0 || psf_id[t] >= n_psf) {
+            fail(LP_E_INVALID, "tile %d: bad size or kernel id", t);
+            delete b;
+            return nullptr;
+        }
+    if (batch_plan(b) != LP_OK) {
+        delete b;
+        return nullptr;
+    }
     return b;
 }
 
@@ -1509,11 +1539,28 @@ int lp_batch_set_output_rows(lp_batch *b, int tile, int64_t first, int64_t count
     if (first < 0 || count < 1 || first + count > b->ny[tile])
         return fail(LP_E_INVALID, "tile %d: rows [%lld, %lld) outside [0, %lld)", tile, (long long)first,
                     (long long)(first + count), (long long)b->ny[tile]);
-    if (b->keep0[tile] != first || b->keep_n[tile] != count) {
-        b->keep0[tile] = first;
-        b->keep_n[tile] = count;
-        b->tables_dirty = true;
+    if (b->keep0[tile] == first && b->keep_n[tile] == count) return LP_OK;
+    const int64_t k0 = b->keep0[tile], kn = b->keep_n[tile];
+    b->keep0[tile] = first;
+    b->keep_n[tile] = count;
+    if (!b->bound && !b->ws) {
+        // before the first bind: the padding classes follow the windows
+        const int rc = batch_plan(b);
+        if (rc != LP_OK) {
+            b->keep0[tile] = k0;
+            b->keep_n[tile] = kn;
+            (void)batch_plan(b);
+            return rc;
+        }
+    } else if (batch_need_y(b, tile) > b->groups[b->item_group[tile]].py) {
+        const int64_t need = batch_need_y(b, tile);
+        b->keep0[tile] = k0;
+        b->keep_n[tile] = kn;
+        return fail(LP_E_STATE, "tile %d: rows [%lld, %lld) need %lld padded rows, more than its class's %lld; "
+                    "set such windows before lp_batch_bind", tile, (long long)first, (long long)(first + count),
+                    (long long)need, (long long)b->groups[b->item_group[tile]].py);
     }
+    b->tables_dirty = true;
     return LP_OK;
 }
 

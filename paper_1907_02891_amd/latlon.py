@@ -14,7 +14,8 @@ east-west), and `LatitudeBands` runs the bands as overlap-save slabs: slab t
 holds its band's rows plus the kernel's reach above and below, all slabs go
 through one batched call (lp_convolve_batched, one launch per stage and
 padding class), and each slab writes only its band's rows of the output
-(lp_batch_set_output_rows), so the stitched map needs no copy.
+(lp_batch_set_output_rows), so the stitched map needs no copy.  With whole
+halos a slab's kept rows need only as many padded rows as the slab has.
 """
 from __future__ import annotations
 
@@ -68,10 +69,12 @@ class LatitudeBands:
         self.slabs = [(max(0, a - above), min(ny, b + below)) for a, b in zip(edges, edges[1:])]
         shapes = [(s1 - s0, nx) for s0, s1 in self.slabs]
         self.batch = lp.Batch(shapes, list(range(len(kernels))), [k.shape for k in kernels], pitch_km=pitch_km)
-        self.batch.bind(device=device, stream=stream)
-        self.batch.set_kernels(kernels)
+        # windows before bind: each slab is padded only as far as its kept
+        # rows need (Py >= slab rows when the halos are whole)
         for t, ((s0, _), a, b) in enumerate(zip(self.slabs, edges, edges[1:])):
             self.batch.set_output_rows(t, a - s0, b - a)
+        self.batch.bind(device=device, stream=stream)
+        self.batch.set_kernels(kernels)
 
     def convolve(self, x, out=None):
         import torch

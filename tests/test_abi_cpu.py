@@ -285,6 +285,33 @@ def test_batch_output_rows_errors():
     assert lib.lp_batch_set_output_rows(b._b, 0, 10, 590) == lp.LP_OK
 
 
+def _need_rows(ny, ky, k0, k1):
+    cy = (ky - 1) // 2
+    return max(k1 + cy, ny + ky - 1 - cy - k0)
+
+
+@pytest.mark.parametrize("ny,ky,k0,k1", [(4048, 2001, 1000, 3048), (4048, 2001, 0, 4048), (1180, 201, 100, 1080),
+                                         (948, 649, 324, 624), (948, 648, 0, 300), (700, 100, 650, 700)])
+def test_batch_windows_replan_padding(ny, ky, k0, k1):
+    """Output-row windows set before bind choose the padding class from
+    max(k1 + cy, ny + ky - 1 - cy - k0): n + floor(k/2) for the whole map,
+    ny for a slab whose kept rows have their whole kernel footprint."""
+    assert _need_rows(ny, ky, 0, ny) == ny + ky // 2
+    b = lp.Batch([(ny, 300)], [0], [(ky, 31)])
+    full = b.groups[0]["padding"][0]
+    bytes_full = b.workspace_bytes
+    b.set_output_rows(0, k0, k1 - k0)
+    need = _need_rows(ny, ky, k0, k1)
+    ly, _ = lp.spec_lengths()
+    py = b.groups[0]["padding"][0]
+    assert py == min(L for L in ly if L >= need)
+    assert py <= full and (py < full) == (b.workspace_bytes < bytes_full)
+    # whole halos: the slab needs no more rows than it has
+    cy = (ky - 1) // 2
+    if k0 >= cy and k1 <= ny - (ky - 1 - cy):
+        assert need == ny
+
+
 def test_band_kernel_matches_oracle_geometry():
     from oracle import latlon as olat
     from paper_1907_02891_amd import latlon

@@ -129,3 +129,33 @@ def test_batched_workload_sampled(lp, torch):
         ref.append(oracle.conv_same_pixels(m, psfs[ids[t]], idx))
     got, ref = np.concatenate(got), np.concatenate(ref)
     check(got, ref, "batched workload sampled")
+
+
+def test_window_padding_slab(lp, torch):
+    """An overlap-save slab: kept rows [k0, k1) with their whole kernel
+    footprint inside the slab, so the class pads to >= ny rows only (1200
+    instead of the full map's 1440); the kept rows equal the oracle's."""
+    rng = np.random.default_rng(71)
+    ny, nx, ky, kx, k0, k1 = 1180, 200, 201, 31, 100, 1080
+    R = rng.random((ny, nx)).astype(np.float32)
+    K = rng.random((ky, kx))
+    b = lp.Batch([(ny, nx)], [0], [K.shape])
+    assert b.groups[0]["padding"][0] == 1440
+    b.set_output_rows(0, k0, k1 - k0)
+    assert b.groups[0]["padding"][0] == 1200
+    b.bind()
+    b.set_kernels([K])
+    out = b.convolve([torch.from_numpy(R).cuda()])[0]
+    torch.cuda.synchronize()
+    assert tuple(out.shape) == (k1 - k0, nx)
+    ref = oracle.conv_same(R, K)[k0:k1]
+    e2, em = oracle.rel_l2(out.cpu().numpy(), ref), oracle.max_err_frac(out.cpu().numpy(), ref)
+    print(f"slab window: rel-L2 {e2:.3e} max-err/max {em:.3e}", flush=True)
+    assert e2 <= 1e-5 and em <= 1e-5
+    # after bind a window needing more rows than the class has is refused
+    with pytest.raises(lp.LPError) as ei:
+        b.set_output_rows(0, 0, ny)
+    assert ei.value.code == lp.LP_E_STATE
+    b.set_output_rows(0, k0 + 10, k1 - k0 - 20)  # a narrower window fits the class
+    out2 = b.convolve([torch.from_numpy(R).cuda()])[0]
+    assert np.array_equal(out2.cpu().numpy(), out.cpu().numpy()[10:-10])

@@ -23,7 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_cols_conv_country4096.txt")
+# rocprofv3 --pmc summaries of the column stage, per workload: one block per
+# column variant (kernel name, FETCH_SIZE / WRITE_SIZE KiB per dispatch, VALU
+# wave-instructions), with the kernel-source hash they were taken on
+PMC_FILES = {"country": os.path.join(ROOT, "profiles", "pmc_cols_conv_country4096.txt"),
+             "continental": os.path.join(ROOT, "profiles", "pmc_cols_conv_continental16384.txt")}
 KERNEL_SOURCES = ["paper_1907_02891_amd/csrc/lp_kernels.hip", "paper_1907_02891_amd/csrc/fft_lds.h",
                   "paper_1907_02891_amd/csrc/fft_reg.h", "paper_1907_02891_amd/csrc/lp_internal.h"]
 
@@ -75,25 +79,28 @@ def model_bytes(ny, nx, py, px, form):
     return path, cols, kh
 
 
-def read_pmc(src_hash):
-    """(HBM bytes, VALU wave-instructions) per column-stage dispatch from a
-    committed rocprofv3 --pmc summary, if it was taken on the current kernel
-    sources (else None for each)."""
-    if not os.path.exists(PMC_FILE):
+def read_pmc(src_hash, workload, config_name, col_variant):
+    """(HBM bytes, VALU wave-instructions) per column-stage dispatch from the
+    committed rocprofv3 --pmc summary of this workload, if it was taken on
+    the current kernel sources, the same configuration and the column
+    variant this run chose (else None for each)."""
+    path = PMC_FILES.get(workload)
+    if path is None or col_variant is None or not os.path.exists(path):
         return None, None
     vals = {}
-    for line in open(PMC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_sha256") != src_hash:
+    if vals.get("source_sha256") != src_hash or vals.get("workload") != config_name:
         return None, None
+    pre = f"variant {col_variant} "
     try:
-        f = float(vals["fetch_kib_per_dispatch"]) * float(vals.get("fetch_scale", 1.0))
-        w = float(vals["write_kib_per_dispatch"]) * float(vals.get("write_scale", 1.0))
+        f = float(vals[pre + "fetch_kib_per_dispatch"]) * float(vals.get("fetch_scale", 1.0))
+        w = float(vals[pre + "write_kib_per_dispatch"]) * float(vals.get("write_scale", 1.0))
     except (KeyError, ValueError):
         return None, None
-    valu = vals.get("valu_wave_instructions_per_dispatch")
+    valu = vals.get(pre + "valu_wave_instructions_per_dispatch")
     return (f + w) * 1024.0, (float(valu) if valu else None)
 
 
@@ -241,7 +248,12 @@ def main():
     four_step = plan.column_split[0] > 1
     path_b, cols_b, kh_b = (model_bytes_four_step if four_step else model_bytes)(ny, nx, py, px, plan.form)
     src_hash = kernel_source_hash()
-    traffic, valu = read_pmc(src_hash)
+    col_variant = plan.variant(lp.STAGE_COLUMNS) if plan.kernels == lp.KERNELS_SPECIALISED and \
+        plan.variant_count(lp.STAGE_COLUMNS) > 0 else None
+    config_name = wl.name if args.padding == "config" else f"{wl.name}-window-p{pad[0]}"
+    traffic, valu = read_pmc(src_hash, args.workload, config_name, col_variant)
+    if args.precision != "fp32":
+        traffic, valu = None, None
     cols_s = stage_avg[1] * 1e-3
     achieved = cols_b / cols_s / 1e9
     col_kernel = "k_cols_reg" if plan.kernels == lp.KERNELS_SPECIALISED else "k_cols_conv"

@@ -219,9 +219,9 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 96, 12, 15, 15, 4, 2, 1},
     {2400, 160, 15, 16, 10, 2, 4, 1},
     {2400, 160, 16, 15, 10, 2, 4, 1},
+    {9216, 384, 24, 24, 16, 2, 0, 1},
     {9216, 384, 16, 24, 24, 1, 2, 1},
     {9216, 256, 16, 24, 24, 2, 2, 1},
-    {9216, 384, 24, 24, 16, 2, 0, 1},
     {9216, 384, 24, 24, 16, 1, 0, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
     {1440, 120, 15, 12, 8, 2, 0, 1},

@@ -354,9 +354,12 @@ int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *co
  * could read rows an earlier one already wrote).
  * Padding (Sec. 2.5): output row i sums input rows i + cy - a over the
  * kernel rows a < ky (cy = (ky - 1) / 2), so on a circle of Py rows the
- * kept rows [k0, k1) stay exact when Py >= max(k1 + cy, ny + ky - 1 - cy
- * - k0): n + floor(k/2) for the whole map, down to ny for a slab that keeps
- * only rows whose kernel footprint lies inside it.  Called before the
+ * kept rows [k0, k1) stay exact when Py >= k1 + cy and, if some kept row
+ * reaches above row 0 (k0 < ky - 1 - cy), also Py >= ny + ky - 1 - cy - k0
+ * (the wrapped rows must be zero padding): n + floor(k/2) for the whole
+ * map, at most ny for a slab that keeps only rows whose kernel footprint
+ * lies inside it (then only the first Py rows are transformed, which are
+ * all the kept rows reach).  Called before the
  * first lp_batch_bind, the padding classes are chosen again from this
  * bound (lp_batch_workspace_bytes changes; per-class variants reset);
  * after it, a window that needs more rows than its map's class has is

@@ -1181,16 +1181,19 @@ hipError_t batch_launch_all(lp_batch *b, hipStream_t s)
 // Padded rows a map needs for its output rows [k0, k1) (Sec. 2.5 with the
 // circular wrap-round made harmless): output row i sums x[i + cy - a] over
 // the kernel rows a < ky, with x = 0 outside [0, ny).  On a circle of Py
-// rows the largest index k1 - 1 + cy must stay below Py, and the most
-// negative one, k0 + cy - (ky - 1), must wrap into the zero rows [ny, Py):
-// Py >= max(k1 + cy, ny + ky - 1 - cy - k0).  For the whole map this is
-// n + floor(k/2); for an overlap-save slab that keeps only rows whose
-// kernel footprint lies inside it, it falls to ny.
+// rows the largest index k1 - 1 + cy must stay below Py (a larger one would
+// wrap onto row 0).  If some kept row also reaches above row 0 (k0 + cy -
+// (ky - 1) < 0), that index wraps to Py + it, which must be a zero row in
+// [ny, Py): Py >= ny + ky - 1 - cy - k0.  For the whole map this is
+// n + floor(k/2); for a slab that keeps only rows whose kernel footprint
+// lies inside it, it is at most ny (the column stage then loads only the
+// first Py rows, which are all the kept rows reach).
 static int64_t batch_need_y(const lp_batch *b, int t)
 {
     const int64_t k = b->ky[b->psf[t]], cy = (k - 1) / 2;
     const int64_t k0 = b->keep0[t], k1 = b->keep0[t] + b->keep_n[t];
-    return std::max(k1 + cy, b->ny[t] + k - 1 - cy - k0);
+    const int64_t top = k1 + cy;
+    return (k0 + cy - (k - 1) >= 0) ? top : std::max(top, b->ny[t] + k - 1 - cy - k0);
 }
 
 // Padding classes and workspace layout from the maps, kernels, output rows

@@ -287,7 +287,7 @@ def test_batch_output_rows_errors():
 
 def _need_rows(ny, ky, k0, k1):
     cy = (ky - 1) // 2
-    return max(k1 + cy, ny + ky - 1 - cy - k0)
+    return k1 + cy if k0 + cy - (ky - 1) >= 0 else max(k1 + cy, ny + ky - 1 - cy - k0)
 
 
 @pytest.mark.parametrize("ny,ky,k0,k1", [(4048, 2001, 1000, 3048), (4048, 2001, 0, 4048), (1180, 201, 100, 1080),
@@ -308,7 +308,9 @@ def test_batch_windows_replan_padding(ny, ky, k0, k1):
     assert py <= full and (py < full) == (b.workspace_bytes < bytes_full)
     # whole halos: the slab needs no more rows than it has
     cy = (ky - 1) // 2
-    if k0 >= cy and k1 <= ny - (ky - 1 - cy):
+    if k0 >= ky - 1 - cy and k1 <= ny - cy:
+        assert need <= ny
+    if k0 == ky - 1 - cy and k1 == ny - cy:
         assert need == ny
 
 

@@ -131,18 +131,23 @@ def test_batched_workload_sampled(lp, torch):
     check(got, ref, "batched workload sampled")
 
 
-def test_window_padding_slab(lp, torch):
+@pytest.mark.parametrize("case", [(1180, 200, 201, 31, 100, 1080, 1440, 1200),   # whole halos: Py >= ny
+                                  (1300, 90, 21, 7, 20, 1180, 1440, 1200)],     # no wrap: Py = 1200 < ny
+                         ids=["halo", "short"])
+def test_window_padding_slab(lp, torch, case):
     """An overlap-save slab: kept rows [k0, k1) with their whole kernel
-    footprint inside the slab, so the class pads to >= ny rows only (1200
-    instead of the full map's 1440); the kept rows equal the oracle's."""
+    footprint inside the slab, so the class pads only as far as the kept
+    rows reach (k1 + cy), here less than the full map's class; in the second
+    case less than the map itself (only the first Py rows are transformed).
+    The kept rows equal the oracle's."""
     rng = np.random.default_rng(71)
-    ny, nx, ky, kx, k0, k1 = 1180, 200, 201, 31, 100, 1080
+    ny, nx, ky, kx, k0, k1, full, cls = case
     R = rng.random((ny, nx)).astype(np.float32)
     K = rng.random((ky, kx))
     b = lp.Batch([(ny, nx)], [0], [K.shape])
-    assert b.groups[0]["padding"][0] == 1440
+    assert b.groups[0]["padding"][0] == full
     b.set_output_rows(0, k0, k1 - k0)
-    assert b.groups[0]["padding"][0] == 1200
+    assert b.groups[0]["padding"][0] == cls
     b.bind()
     b.set_kernels([K])
     out = b.convolve([torch.from_numpy(R).cuda()])[0]

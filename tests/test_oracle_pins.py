@@ -385,3 +385,59 @@ def test_class_sum_pixels_match_full_field():
     full = oracle.conv_same_classes(Rs, Ks).ravel()
     idx = rng.choice(full.size, 40, replace=False)
     np.testing.assert_allclose(oracle.conv_same_classes_pixels(Rs, Ks, idx), full[idx], rtol=1e-13)
+
+
+def _kept_rows_need(ny, ky, k0, k1):
+    """Padded length the library uses for kept output rows [k0, k1) (the
+    batch's window bound): k1 + cy, and at least ny + ky - 1 - cy - k0 when
+    some kept row reaches above row 0."""
+    cy = (ky - 1) // 2
+    return k1 + cy if k0 + cy - (ky - 1) >= 0 else max(k1 + cy, ny + ky - 1 - cy - k0)
+
+
+def _same_1d(x, K, cy):
+    """Direct "same" convolution along one axis (Eq. 7, zero outside)."""
+    n = len(x)
+    return np.array([sum(K[a] * x[i + cy - a] for a in range(len(K)) if 0 <= i + cy - a < n) for i in range(n)])
+
+
+def _circular_1d(x, K, cy, P):
+    """The same sums on a circle of P samples holding the first min(n, P)
+    input samples (zero-extended when n < P), i.e. what a length-P transform
+    of the loaded rows computes (Eq. 9); rows >= P are not loaded.  Outputs
+    for i < min(n, P)."""
+    xp = np.zeros(P)
+    m = min(len(x), P)
+    xp[:m] = x[:m]
+    return np.array([sum(K[a] * xp[(i + cy - a) % P] for a in range(len(K))) for i in range(m)])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_kept_rows_padding_bound_is_exact_and_tight(seed):
+    """Brute force on small 1-D cases: with P = the window bound the kept
+    rows of the circular convolution equal the linear ones; with P - 1 some
+    kept row differs.  The whole window gives n + floor(k/2); whole halos
+    give n; a window whose footprint never wraps may need fewer rows than n
+    (then only the first P input rows are loaded, and the kept rows reach no
+    further)."""
+    rng = np.random.default_rng(seed)
+    ny = int(rng.integers(3, 40))
+    ky = int(rng.integers(1, 2 * ny))
+    k0 = int(rng.integers(0, ny))
+    k1 = int(rng.integers(k0 + 1, ny + 1))
+    x = rng.random(ny) + 0.5
+    K = rng.random(ky) + 0.5
+    cy = (ky - 1) // 2
+    need = _kept_rows_need(ny, ky, k0, k1)
+    assert _kept_rows_need(ny, ky, 0, ny) == ny + ky // 2
+    ref = _same_1d(x, K, cy)
+    got = _circular_1d(x, K, cy, need)
+    np.testing.assert_allclose(got[k0:k1], ref[k0:k1], rtol=1e-13, atol=0)
+    assert need >= k1
+    if need - 1 >= k1:
+        bad = _circular_1d(x, K, cy, need - 1)
+        assert np.max(np.abs(bad[k0:k1] - ref[k0:k1])) > 1e-6
+    if k0 >= ky - 1 - cy and k1 <= ny - cy:
+        assert need <= ny
+    if k0 == ky - 1 - cy and k1 == ny - cy:
+        assert need == ny

@@ -714,7 +714,7 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
         const int i = lp::row_spec_index(static_cast<int>(p->m), k);
         if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
         const lp::RowSpec c = lp::kRowSpecs[i];
-        const int t[9] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, 0};
+        const int t[9] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half};
         std::copy(t, t + 9, v);
     } else if (stage == LP_STAGE_COLUMNS) {
         const int i = lp::col_spec_index(static_cast<int>(p->py), k);

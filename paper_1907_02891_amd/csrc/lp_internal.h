@@ -203,6 +203,7 @@ namespace lp {
 // next tile prefetched).
 struct RowSpec {
     int m, tf, r0, r1, r2, b, occ, pf;
+    int half = 0;  // exchanges in two halves (half the LDS); occ is then exact, pf must be 1
 };
 constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 2, 4, 1},
@@ -217,6 +218,8 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 4, 2, 0},
     {2700, 128, 15, 15, 12, 6, 2, 1},
     {2700, 96, 12, 15, 15, 4, 2, 1},
+    {2700, 180, 20, 15, 9, 2, 6, 1, 1},
+    {2700, 128, 15, 15, 12, 2, 4, 1, 1},
     {2400, 160, 15, 16, 10, 2, 4, 1},
     {2400, 160, 16, 15, 10, 2, 4, 1},
     {9216, 384, 24, 24, 16, 2, 0, 1},

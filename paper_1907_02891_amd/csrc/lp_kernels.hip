@@ -1191,18 +1191,267 @@ int row_spec_count(int m)
 
 int row_spec_rows(int idx) { return kRowSpecs[idx].b; }
 
+// Row kernels with the exchanges in two halves (one tile per workgroup): the
+// same transforms and layouts as k_rows_r2c_reg / k_rows_c2r_reg, but each
+// exchange between passes goes through a float buffer of the same word
+// layout twice, real parts then imaginary parts, so the buffer is half the
+// size and more workgroups fit on a CU while others wait on HBM.  The
+// register allocator plans for exactly OCC waves per SIMD.
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+k_rows_r2c_half(const float *__restrict__ Rm, float2 *__restrict__ W, RowRegArgs a,
+                const BatchItem *__restrict__ items)
+{
+    extern __shared__ float2 lds[];
+    float *f = reinterpret_cast<float *>(lds);
+    using F0 = RegPass<M, R0, 1, TF, B, 0>;
+    using F1 = RegPass<M, R1, R0, TF, B, R0>;
+    constexpr int NB = M / R2;
+    static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        Rm = it.in;
+        W = it.w;
+        a.ny = it.ny;
+        a.nx = it.nx;
+    }
+    const int ntiles = (a.ny + B - 1) / B;
+    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
+    if (t0 >= ntiles) return;
+    const int tt = threadIdx.x / B, b = threadIdx.x % B;
+    const int row = t0 * B + b;
+    const bool rv = row < a.ny;
+    const int64_t ny = a.ny;
+
+    float2 x0[F0::S][R0];
+    {
+        const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
+#pragma unroll
+        for (int s = 0; s < F0::S; ++s) {
+            const int i = tt + s * TF;
+            if (F0::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) x0[s][j] = load_pair<EVEN_NX>(src, i + j * F0::NB, a.nx, rv);
+            }
+        }
+    }
+    F0::template butterfly<false>(x0, tt);
+    F0::template store_part<0>(x0, f, tt, b);
+    __syncthreads();
+    float2 x1[F1::S][R1];
+    F1::template load_part<0>(x1, f, tt, b);
+    __syncthreads();
+    F0::template store_part<1>(x0, f, tt, b);
+    __syncthreads();
+    F1::template load_part<1>(x1, f, tt, b);
+    F1::template twiddle<false>(x1, a.tw_f1, tt);
+    F1::template butterfly<false>(x1, tt);
+    __syncthreads();
+    F1::template store_part<0>(x1, f, tt, b);
+    __syncthreads();
+    // last pass: thread tt takes butterflies tt and NB - tt (as in k_rows_r2c_reg)
+    const bool pairer = tt <= NB / 2;
+    const int i1 = tt, i2 = NB - tt;
+    const bool two = pairer && (i2 != i1) && (i2 < NB);
+    float2 z1[R2], z2[R2];
+    if (pairer) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) z1[j].x = f[(i1 + j * NB) * B + b];
+        if (two) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) z2[j].x = f[(i2 + j * NB) * B + b];
+        }
+    }
+    __syncthreads();
+    F1::template store_part<1>(x1, f, tt, b);
+    __syncthreads();
+    if (pairer) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) z1[j].y = f[(i1 + j * NB) * B + b];
+        if (i1 > 0) {
+#pragma unroll
+            for (int j = 1; j < R2; ++j) z1[j] = cmul(z1[j], a.tw_f2[i1 * (R2 - 1) + j - 1]);
+        }
+        dftc<R2, false>(z1);
+        if (two) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) z2[j].y = f[(i2 + j * NB) * B + b];
+#pragma unroll
+            for (int j = 1; j < R2; ++j) z2[j] = cmul(z2[j], a.tw_f2[i2 * (R2 - 1) + j - 1]);
+            dftc<R2, false>(z2);
+        }
+        if (rv) {
+            // X[k] of this row at ((k / C) * ny + row) * C + k % C
+            const int lc = a.lc, cm = (1 << lc) - 1;
+            float2 *dst = W + (static_cast<int64_t>(row) << lc);
+            auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
+            if (i1 == 0) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) {
+                    const int k = j * NB;
+                    dst[at(k)] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+                }
+                dst[at(M)] = r2c_split(z1[0], z1[0], a.rtw[M]);
+            } else if (!two) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) {
+                    const int k = i1 + j * NB;
+                    dst[at(k)] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) {
+                    const int k1 = i1 + j * NB, k2 = i2 + j * NB;
+                    dst[at(k1)] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
+                    dst[at(k2)] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                }
+            }
+        }
+    }
+}
+
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, bool EVEN_NX>
+__global__ void __launch_bounds__(TF * B) __attribute__((amdgpu_waves_per_eu(OCC, OCC)))
+k_rows_c2r_half(const float2 *__restrict__ W, float *__restrict__ Sm, RowRegArgs a,
+                const BatchItem *__restrict__ items)
+{
+    extern __shared__ float2 lds[];
+    float *f = reinterpret_cast<float *>(lds);
+    using I1 = RegPass<M, R1, R2, TF, B, R2>;
+    using I2 = RegPass<M, R0, R2 * R1, TF, B, 0>;
+    constexpr int NB = M / R2;
+    static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
+    if (items) {
+        const BatchItem &it = items[blockIdx.y];
+        W = it.w;
+        Sm = it.out;
+        a.ny = it.ny;
+        a.nx = it.nx;
+        a.keep0 = it.keep0;
+        a.keep1 = it.keep1;
+    }
+    const int ntiles = (a.ny + B - 1) / B;
+    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
+    if (t0 >= ntiles) return;
+    // a tile with no row to keep does nothing (uniform over the workgroup)
+    if (t0 * B >= a.keep1 || (t0 + 1) * B <= a.keep0) return;
+    const int tt = threadIdx.x / B, b = threadIdx.x % B;
+    const int row = t0 * B + b;
+    const bool rv = row >= a.keep0 && row < a.keep1;
+    const int64_t ny = a.ny;
+    const bool pairer = tt <= NB / 2;
+    const int i1 = tt, i2 = NB - tt;
+    const bool two = pairer && (i2 != i1) && (i2 < NB);
+
+    // first pass: thread tt takes butterflies tt and NB - tt, merging X[k]
+    // and X[M - k] in registers (as in k_rows_c2r_reg)
+    float2 za[R2], zb[R2];
+    if (pairer) {
+        float2 xa[R2], xb[R2], xm = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < R2; ++j) {
+            xa[j] = make_float2(0.f, 0.f);
+            xb[j] = make_float2(0.f, 0.f);
+        }
+        if (rv) {
+            const int lc = a.lc, cm = (1 << lc) - 1;
+            const float2 *src = W + (static_cast<int64_t>(row) << lc);
+            auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
+#pragma unroll
+            for (int j = 0; j < R2; ++j) xa[j] = src[at(i1 + j * NB)];
+            if (two) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) xb[j] = src[at(i2 + j * NB)];
+            }
+            if (i1 == 0) xm = src[at(M)];
+        }
+        if (i1 == 0) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], j ? xa[(R2 - j) % R2] : xm, a.rtw[j * NB]);
+        } else if (!two) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) za[j] = c2r_merge(xa[j], xa[R2 - 1 - j], a.rtw[i1 + j * NB]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) {
+                za[j] = c2r_merge(xa[j], xb[R2 - 1 - j], a.rtw[i1 + j * NB]);
+                zb[j] = c2r_merge(xb[j], xa[R2 - 1 - j], a.rtw[i2 + j * NB]);
+            }
+        }
+        dftc<R2, true>(za);
+#pragma unroll
+        for (int j = 0; j < R2; ++j) f[(i1 * lds_pitch(R2) + j) * B + b] = za[j].x;
+        if (two) {
+            dftc<R2, true>(zb);
+#pragma unroll
+            for (int j = 0; j < R2; ++j) f[(i2 * lds_pitch(R2) + j) * B + b] = zb[j].x;
+        }
+    }
+    __syncthreads();
+    float2 y1[I1::S][R1];
+    I1::template load_part<0>(y1, f, tt, b);
+    __syncthreads();
+    if (pairer) {
+#pragma unroll
+        for (int j = 0; j < R2; ++j) f[(i1 * lds_pitch(R2) + j) * B + b] = za[j].y;
+        if (two) {
+#pragma unroll
+            for (int j = 0; j < R2; ++j) f[(i2 * lds_pitch(R2) + j) * B + b] = zb[j].y;
+        }
+    }
+    __syncthreads();
+    I1::template load_part<1>(y1, f, tt, b);
+    I1::template twiddle<true>(y1, a.tw_i1, tt);
+    I1::template butterfly<true>(y1, tt);
+    __syncthreads();
+    I1::template store_part<0>(y1, f, tt, b);
+    __syncthreads();
+    float2 y2[I2::S][R0];
+    I2::template load_part<0>(y2, f, tt, b);
+    __syncthreads();
+    I1::template store_part<1>(y1, f, tt, b);
+    __syncthreads();
+    I2::template load_part<1>(y2, f, tt, b);
+    I2::template twiddle<true>(y2, a.tw_i2, tt);
+    I2::template butterfly<true>(y2, tt);
+    if (rv) {
+        float *dst = Sm + static_cast<int64_t>(row - a.keep0) * a.nx;
+#pragma unroll
+        for (int s = 0; s < I2::S; ++s) {
+            const int i = tt + s * TF;
+            if (I2::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) {
+                    const int c0 = 2 * (i + j * I2::NB);
+                    if (EVEN_NX) {
+                        if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
+                    } else {
+                        if (c0 < a.nx) dst[c0] = y2[s][j].x;
+                        if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int I>
 static constexpr size_t row_lds_bytes()
 {
     constexpr RowSpec c = kRowSpecs[I];
-    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * 8;
+    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * (c.half ? 4 : 8);
 }
 
 template <int I, bool FWD, bool EVEN>
 static const void *row_fn()
 {
     constexpr RowSpec c = kRowSpecs[I];
-    if constexpr (FWD)
+    static_assert(!c.half || c.pf == 1, "half-exchange rows take one tile per workgroup");
+    if constexpr (c.half && FWD)
+        return reinterpret_cast<const void *>(&k_rows_r2c_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
+    else if constexpr (c.half)
+        return reinterpret_cast<const void *>(&k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
+    else if constexpr (FWD)
         return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
     else
         return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
@@ -1262,7 +1511,19 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
         const dim3 g(groups, nitems), t(c.tf * c.b);
         const size_t lds = row_lds_bytes<I>();
         const bool even = (a.nx % 2) == 0;
-        if (fwd) {
+        if constexpr (c.half) {
+            if (fwd) {
+                const float *R = static_cast<const float *>(in);
+                float2 *W = static_cast<float2 *>(out);
+                if (even) hipLaunchKernelGGL((k_rows_r2c_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, R, W, a, items);
+                else hipLaunchKernelGGL((k_rows_r2c_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, R, W, a, items);
+            } else {
+                const float2 *W = static_cast<const float2 *>(in);
+                float *S = static_cast<float *>(out);
+                if (even) hipLaunchKernelGGL((k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, W, S, a, items);
+                else hipLaunchKernelGGL((k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, W, S, a, items);
+            }
+        } else if (fwd) {
             const float *R = static_cast<const float *>(in);
             float2 *W = static_cast<float2 *>(out);
             if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, R, W, a, items);

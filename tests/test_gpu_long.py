@@ -44,6 +44,7 @@ CASES = [  # ny, nx, ky, kx, padding (None: default), symmetric kernel, expected
     (20000, 4, 1001, 3, (20736, 6), False, (2, 10368)),   # the window bound n + floor(k/2) = 20500
     (60000, 3, 3001, 3, None, True, (4, 16000)),          # Py 64000
     (75000, 3, 3001, 1, None, False, (5, 15625)),         # Py 78125 = 5^7
+    (130000, 2, 1001, 1, None, True, (8, 16384)),         # Py 131072 = LP_MAX_PY
 ]
 
 

@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--padding", default="config", choices=["config", "window"],
                     help="config: the workload's padded size; window: the smallest size that still "
                          "gives the exact input-sized window (n + floor(k/2) per axis)")
+    ap.add_argument("--pad", default=None,
+                    help="PY,PX: explicit padded sizes (>= n + floor(k/2), 5-smooth, PX even) instead of --padding")
     ap.add_argument("--variants", default=None,
                     help="ROWS,COLUMNS[,ROWS_INVERSE]: run these specialised variants instead of autotuning")
     args = ap.parse_args()
@@ -200,6 +202,8 @@ def main():
 
     t0 = time.perf_counter()
     pad = (wl.py, wl.px) if args.padding == "config" else lp.window_padding(ny, nx, *K.shape)
+    if args.pad:
+        pad = tuple(int(v) for v in args.pad.split(","))
     plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=pad)
     mode, dtype, what = PRECISIONS[args.precision]
     plan.set_precision(mode)
@@ -250,7 +254,7 @@ def main():
     src_hash = kernel_source_hash()
     col_variant = plan.variant(lp.STAGE_COLUMNS) if plan.kernels == lp.KERNELS_SPECIALISED and \
         plan.variant_count(lp.STAGE_COLUMNS) > 0 else None
-    config_name = wl.name if args.padding == "config" else f"{wl.name}-window-p{pad[0]}"
+    config_name = wl.name if args.padding == "config" and not args.pad else f"{wl.name}-p{pad[0]}x{pad[1]}"
     traffic, valu = read_pmc(src_hash, args.workload, config_name, col_variant)
     if args.precision != "fp32":
         traffic, valu = None, None
@@ -288,7 +292,7 @@ def main():
         "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": dtype, "data": "synthetic",
-        "config": {"workload": wl.name if args.padding == "config" else f"{wl.name}-window-p{pad[0]}",
+        "config": {"workload": config_name,
                    "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
                    "padding": [py, px], "pitch_km": wl.pitch_km,
                    "spectrum_form": {1: "real-quadrant", 2: "complex"}[plan.form],

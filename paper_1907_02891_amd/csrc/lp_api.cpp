@@ -211,6 +211,7 @@ struct lp_plan {
     // four-step column stage (padded columns longer than one LDS tile)
     bool long_cols = false;
     int64_t p1 = 1, p2 = 0;
+    int mid_spec = -1;  // column specialisation of the middle transforms (length P2), or -1
     int long_logb = 0, t_outer = 64, t_mid = 64;
     // register-resident column stage (if the padded column length has one)
     int col_spec = -1;
@@ -276,10 +277,11 @@ void layout(lp_plan *p)
 }
 
 // Four-step split of a padded column longer than one LDS tile: P2 the
-// largest divisor of Py within a tile (the fused middle transform), P1 =
-// Py / P2 (the outer transforms, 2^logb of them per workgroup: about 4096
-// values, so that the short outer transforms still fill a workgroup and the
-// reads of consecutive n2 make long runs).
+// longest divisor of Py that has a column specialisation (the middle
+// transforms then run in registers), else the largest divisor within a tile
+// (LDS passes); P1 = Py / P2 (the outer transforms, 2^logb of them per
+// workgroup: about 4096 values, so that the short outer transforms still
+// fill a workgroup and the reads of consecutive n2 make long runs).
 void plan_long_columns(lp_plan *p)
 {
     p->long_cols = p->py > lp::kMaxColLen;
@@ -288,11 +290,20 @@ void plan_long_columns(lp_plan *p)
     if (!p->long_cols) {
         p->p1 = 1;
         p->p2 = 0;
+        p->mid_spec = -1;
         return;
     }
     int64_t p2 = 1;
+    p->mid_spec = -1;
     for (int64_t d = lp::kMaxColLen; d >= 2; --d)
-        if (p->py % d == 0) { p2 = d; break; }
+        if (p->py % d == 0 && p->py / d <= 4096 && lp::long_mid_spec(static_cast<int>(d)) >= 0) {
+            p2 = d;
+            p->mid_spec = lp::long_mid_spec(static_cast<int>(d));
+            break;
+        }
+    if (p->mid_spec < 0)
+        for (int64_t d = lp::kMaxColLen; d >= 2; --d)
+            if (p->py % d == 0) { p2 = d; break; }
     p->p2 = p2;
     p->p1 = p->py / p2;
     int logb = 0;
@@ -341,6 +352,10 @@ void build_spec_tables(lp_plan *p)
     p->twc.clear();
     if (p->col_spec >= 0) {
         const lp::ColSpec c = lp::kColSpecs[p->col_spec];
+        spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
+    } else if (p->long_cols && p->mid_spec >= 0) {
+        // the four-step middle transforms (length P2)
+        const lp::ColSpec c = lp::kColSpecs[p->mid_spec];
         spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
     }
     // forward tables from the forward row variant, inverse ones from the
@@ -409,6 +424,10 @@ int set_padding(lp_plan *p, int64_t py, int64_t px)
     p->twc_max = p->twr_max = 2;
     for (int k = 0; k < lp::col_spec_count(static_cast<int>(py)); ++k) {
         const lp::ColSpec c = lp::kColSpecs[lp::col_spec_index(static_cast<int>(py), k)];
+        p->twc_max = std::max<size_t>(p->twc_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
+    }
+    if (p->mid_spec >= 0) {
+        const lp::ColSpec c = lp::kColSpecs[p->mid_spec];
         p->twc_max = std::max<size_t>(p->twc_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
     }
     for (int k = 0; k < lp::row_spec_count(static_cast<int>(p->m)); ++k) {
@@ -523,8 +542,14 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         la.twq = reinterpret_cast<const float2 *>(p->ws + p->off_twq);
         la.T = reinterpret_cast<float2 *>(p->ws + p->off_t);
         la.kh = ca.kh;
+        lp::ColRegArgs mr{};
+        const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
+        mr.tw_f1 = twc + p->twc_off[0];
+        mr.tw_f2 = twc + p->twc_off[1];
+        mr.tw_i1 = twc + p->twc_off[2];
+        mr.tw_i2 = twc + p->twc_off[3];
         if ((e = lp::launch_long_cols(W, la, static_cast<int>(p->h), p->form, adjoint, p->t_outer, p->t_mid,
-                                      p->stream)) != hipSuccess)
+                                      p->stream, spec_ok ? p->mid_spec : -1, &mr)) != hipSuccess)
             return fail_hip(e, "four-step column stage launch");
     } else if (p->col_spec >= 0 && spec_ok) {
         lp::ColRegArgs cr{};

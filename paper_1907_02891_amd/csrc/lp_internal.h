@@ -111,8 +111,13 @@ struct LongArgs {
     const void *kh;      // spectrum (float real form or float2), stored row
                          // r = k1 P2 + k2 of column v at ((v >> lc) Py + r) << lc | (v & (2^lc - 1))
 };
+struct ColRegArgs;
+// mid_spec >= 0: the middle transforms with the register kernels of column
+// specialisation mid_spec (its length must be P2; tables in *mid), else the
+// LDS passes of a.f2.
 hipError_t launch_long_cols(float2 *W, const LongArgs &a, int ncols, int form, bool conj_k,
-                            int threads_outer, int threads_mid, hipStream_t s);
+                            int threads_outer, int threads_mid, hipStream_t s, int mid_spec = -1,
+                            const ColRegArgs *mid = nullptr);
 hipError_t set_long_attributes();
 
 }  // namespace lp
@@ -187,6 +192,10 @@ struct BatchItem {
 // Index of the k-th specialisation for column length n, or -1; number of them.
 int col_spec_index(int n, int k = 0);
 int col_spec_count(int n);
+int long_mid_spec(int n);  // specialisation for four-step middle transforms of length n (-1: none)
+hipError_t launch_long_mid_reg(const LongArgs &a, const ColRegArgs &c, int idx, int ncols, int form, bool conj_k,
+                               hipStream_t s);
+hipError_t set_long_mid_attributes();
 hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, int form, bool conj_k,
                            hipStream_t s, const BatchItem *items = nullptr, int nitems = 1,
                            bool class_sum = false);

@@ -757,6 +757,173 @@ static constexpr int xchg_words(int n, int r0, int r2)
     return m > n ? m : n;
 }
 
+// Middle kernel of the four-step column stage with register-resident
+// transforms, for a split whose P2 has a specialisation: workgroup (v, k1)
+// takes the P2 values T[v][k1][.] (contiguous), transforms them with the
+// passes of k_cols_reg (radices R0, R1, R2), multiplies by the spectrum at
+// stored rows k1 P2 + k2 (the four-step order, contiguous), transforms back
+// and multiplies by exp(+2 pi i n2 k1 / Py), in place.  Tables: c.tw_* for
+// length P2; a.twq for the four-step twiddles.
+template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ>
+__global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_long_mid_reg(LongArgs a, ColRegArgs c)
+{
+    extern __shared__ float2 lds[];
+    using F0 = RegPass<N, R0, 1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using I0 = RegPass<N, R2, 1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
+    const int tt = threadIdx.x;
+    const bool act = tt < TF;
+    const int v = blockIdx.x, k1 = blockIdx.y;
+    float2 *t = a.T + static_cast<int64_t>(v) * a.py + static_cast<int64_t>(k1) * N;
+    float2 x0[F0::S][R0];
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < F0::S; ++s) {
+            const int i = tt + s * TF;
+            if (F0::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) x0[s][j] = t[i + j * F0::NB];
+            }
+        }
+        F0::template butterfly<false>(x0, tt);
+        F0::store(x0, lds, tt, 0);
+    }
+    __syncthreads();
+    float2 x1[F1::S][R1];
+    if (act) {
+        F1::load(x1, lds, tt, 0);
+        F1::template twiddle<false>(x1, c.tw_f1, tt);
+        F1::template butterfly<false>(x1, tt);
+    }
+    __syncthreads();
+    if (act) F1::store(x1, lds, tt, 0);
+    __syncthreads();
+    float2 x2[F2::S][R2];
+    if (act) {
+        F2::load(x2, lds, tt, 0);
+        F2::template twiddle<false>(x2, c.tw_f2, tt);
+        F2::template butterfly<false>(x2, tt);
+        // Eq. 9: frequency k1 + P1 k2 with k2 = u = i + j NB, stored row k1 P2 + k2
+        const int lc = a.lc, cm = (1 << lc) - 1;
+        const int64_t base = ((static_cast<int64_t>(v >> lc) * a.py + static_cast<int64_t>(k1) * N) << lc) + (v & cm);
+#pragma unroll
+        for (int s = 0; s < F2::S; ++s) {
+            const int i = tt + s * TF;
+            if (F2::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) {
+                    const int64_t idx = base + (static_cast<int64_t>(i + j * F2::NB) << lc);
+                    if constexpr (FORM == 1) {
+                        x2[s][j] = cscale(x2[s][j], static_cast<const float *>(a.kh)[idx]);
+                    } else {
+                        const float2 k = static_cast<const float2 *>(a.kh)[idx];
+                        x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
+                    }
+                }
+            }
+        }
+        I0::template butterfly<true>(x2, tt);
+    }
+    __syncthreads();
+    if (act) I0::store(x2, lds, tt, 0);
+    __syncthreads();
+    float2 y1[I1::S][R1];
+    if (act) {
+        I1::load(y1, lds, tt, 0);
+        I1::template twiddle<true>(y1, c.tw_i1, tt);
+        I1::template butterfly<true>(y1, tt);
+    }
+    __syncthreads();
+    if (act) I1::store(y1, lds, tt, 0);
+    __syncthreads();
+    if (act) {
+        float2 y2[I2::S][R0];
+        I2::load(y2, lds, tt, 0);
+        I2::template twiddle<true>(y2, c.tw_i2, tt);
+        I2::template butterfly<true>(y2, tt);
+#pragma unroll
+        for (int s = 0; s < I2::S; ++s) {
+            const int i = tt + s * TF;
+            if (I2::valid(i)) {
+#pragma unroll
+                for (int j = 0; j < R0; ++j) {
+                    const int n = i + j * I2::NB;
+                    // n k1 < P2 P1 = Py: no reduction needed
+                    t[n] = cmulc(y2[s][j], a.twq[n * k1]);
+                }
+            }
+        }
+    }
+}
+
+// The specialisation the four-step middle kernel uses for a length: the
+// first full-exchange column variant of that length (-1: none).
+int long_mid_spec(int n)
+{
+    for (int i = 0; i < kNumColSpecs; ++i)
+        if (kColSpecs[i].n == n && !kColSpecs[i].half) return i;
+    return -1;
+}
+
+static constexpr bool is_long_mid_spec(int I)
+{
+    for (int i = 0; i < I; ++i)
+        if (kColSpecs[i].n == kColSpecs[I].n && !kColSpecs[i].half) return false;
+    return !kColSpecs[I].half;
+}
+
+template <int I>
+static hipError_t long_mid_from(int idx, const LongArgs &a, const ColRegArgs &c, int ncols, int form,
+                                bool conj_k, hipStream_t s, bool attrs_only)
+{
+    if constexpr (I >= kNumColSpecs) {
+        return attrs_only ? hipSuccess : hipErrorInvalidValue;
+    } else if constexpr (!is_long_mid_spec(I)) {
+        return long_mid_from<I + 1>(idx, a, c, ncols, form, conj_k, s, attrs_only);
+    } else {
+        constexpr ColSpec cs = kColSpecs[I];
+        constexpr size_t lds = static_cast<size_t>(xchg_words(cs.n, cs.r0, cs.r2)) * 8;
+        if (attrs_only) {
+            const void *fns[] = {
+                reinterpret_cast<const void *>(&k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 1, false>),
+                reinterpret_cast<const void *>(&k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 2, false>),
+                reinterpret_cast<const void *>(&k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 2, true>)};
+            for (const void *f : fns) {
+                hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+                if (e != hipSuccess) return e;
+            }
+            return long_mid_from<I + 1>(idx, a, c, ncols, form, conj_k, s, attrs_only);
+        }
+        if (idx != I) return long_mid_from<I + 1>(idx, a, c, ncols, form, conj_k, s, attrs_only);
+        if (a.p2 != cs.n) return hipErrorInvalidValue;
+        const dim3 g(ncols, a.p1), t(((cs.tf + 63) / 64) * 64);
+        if (form == 1)
+            hipLaunchKernelGGL((k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 1, false>), g, t, lds, s, a, c);
+        else if (conj_k)
+            hipLaunchKernelGGL((k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 2, true>), g, t, lds, s, a, c);
+        else
+            hipLaunchKernelGGL((k_long_mid_reg<cs.n, cs.tf, cs.r0, cs.r1, cs.r2, cs.occ, 2, false>), g, t, lds, s, a, c);
+        return hipGetLastError();
+    }
+}
+
+hipError_t launch_long_mid_reg(const LongArgs &a, const ColRegArgs &c, int idx, int ncols, int form, bool conj_k,
+                               hipStream_t s)
+{
+    return long_mid_from<0>(idx, a, c, ncols, form, conj_k, s, false);
+}
+
+hipError_t set_long_mid_attributes()
+{
+    LongArgs a{};
+    ColRegArgs c{};
+    return long_mid_from<0>(-1, a, c, 0, 1, false, nullptr, true);
+}
+
+
 template <int I>
 static constexpr size_t col_lds_bytes()
 {

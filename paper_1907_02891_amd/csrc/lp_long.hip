@@ -17,10 +17,12 @@
 //   k_long_mid  workgroup (v, k1): length-P2 DFT of T[v][k1][.], product
 //               with the spectrum at frequency k1 + P1 k2 (stored in this
 //               order, so the read is contiguous), inverse length-P2 DFT,
-//               times w_Py^(-n2 k1), back in place;
+//               times w_Py^(-n2 k1), back in place (k_long_mid_reg, with
+//               the register-resident passes, when P2 has a column
+//               specialisation);
 //   k_long_inv  workgroup (v, n2 group): inverse length-P1 DFTs, rows
 //               n < ny written back to the intermediate.
-// The transforms are the LDS Stockham passes of the generic kernels
+// The outer transforms are the LDS Stockham passes of the generic kernels
 // (radix 2/3/4/5/8, FP32).  HBM traffic is three passes over a Py-long
 // scratch column instead of one over the ny stored rows: this path exists
 // for sizes the single-tile kernels cannot take, not for speed.
@@ -112,7 +114,8 @@ __global__ void __launch_bounds__(1024) k_long_inv(float2 *__restrict__ W, LongA
 }  // namespace
 
 hipError_t launch_long_cols(float2 *W, const LongArgs &a, int ncols, int form, bool conj_k,
-                            int threads_outer, int threads_mid, hipStream_t s)
+                            int threads_outer, int threads_mid, hipStream_t s, int mid_spec,
+                            const ColRegArgs *mid)
 {
     if (a.p1 < 2 || a.p2 < 2 || static_cast<int64_t>(a.p1) * a.p2 != a.py || a.p2 > kMaxColLen ||
         (a.p1 << a.logb) > kMaxColLen || a.p1 > 65535 || !a.T || !a.kh)
@@ -124,12 +127,18 @@ hipError_t launch_long_cols(float2 *W, const LongArgs &a, int ncols, int form, b
     const dim3 go(ncols, (a.p2 + (1 << a.logb) - 1) >> a.logb), gm(ncols, a.p1);
     const size_t lo = static_cast<size_t>(a.p1) << a.logb << 3, lm = static_cast<size_t>(a.p2) << 3;
     hipLaunchKernelGGL(k_long_fwd, go, dim3(threads_outer), lo, s, W, a);
-    if (form == 1)
+    if (mid_spec >= 0) {
+        if (!mid) return hipErrorInvalidValue;
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if ((e = launch_long_mid_reg(a, *mid, mid_spec, ncols, form, conj_k, s)) != hipSuccess) return e;
+    } else if (form == 1) {
         hipLaunchKernelGGL((k_long_mid<1, false>), gm, dim3(threads_mid), lm, s, a);
-    else if (conj_k)
+    } else if (conj_k) {
         hipLaunchKernelGGL((k_long_mid<2, true>), gm, dim3(threads_mid), lm, s, a);
-    else
+    } else {
         hipLaunchKernelGGL((k_long_mid<2, false>), gm, dim3(threads_mid), lm, s, a);
+    }
     hipLaunchKernelGGL(k_long_inv, go, dim3(threads_outer), lo, s, W, a);
     return hipGetLastError();
 }
@@ -147,7 +156,7 @@ hipError_t set_long_attributes()
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return set_long_mid_attributes();
 }
 
 }  // namespace lp

@@ -138,8 +138,10 @@ COUNTRY = Workload("country-4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 54
 CONTINENTAL = Workload("continental-16384x16384-psf2001-p18432", 16384, 16384, 2001, 2001,
                        18432, 18432, 0.5, 1002)
 ADJOINT = Workload("adjoint-2048x2048-psf801-p2880", 2048, 2048, 801, 801, 2880, 2880, 0.5, 1004)
-# longer than one LDS tile per column: the four-step column stage
-LARGE = Workload("large-24000x24000-psf2001-p26244", 24000, 24000, 2001, 2001, 26244, 26244, 0.5, 1006)
+# longer than one LDS tile per column: the four-step column stage; 27000 =
+# 5 x 5400 (>= n + k - 1 = 26000) lets the middle transforms use the 5400-point
+# register kernels (26244, the smallest 5-smooth size, has no specialised divisor)
+LARGE = Workload("large-24000x24000-psf2001-p27000", 24000, 24000, 2001, 2001, 27000, 27000, 0.5, 1006)
 BATCHED_SEED = 1003
 CLASSES = Workload("classes-3x4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 5400, 5400, 0.5, 1005)
 

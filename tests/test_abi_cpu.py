@@ -50,21 +50,24 @@ def test_create_rejects_oversize(shape):
     assert ei.value.code == lp.LP_E_SIZE
 
 
-def _largest_divisor_within(n, cap):
-    return max(d for d in range(2, cap + 1) if n % d == 0)
+def _four_step_p2(n, cap):
+    """P2 of the four-step split: the longest divisor with a column
+    specialisation (and P1 <= 4096), else the largest divisor within a tile."""
+    spec = [d for d in lp.spec_lengths()[0] if d <= cap and n % d == 0 and n // d <= 4096]
+    return max(spec) if spec else max(d for d in range(2, cap + 1) if n % d == 0)
 
 
 @pytest.mark.parametrize("shape", [(20000, 4, 1001, 3), (24000, 24000, 2001, 2001), (60000, 10, 3001, 3),
                                    (75000, 3, 3001, 1), (130000, 2, 1001, 1)])
 def test_four_step_column_split(shape):
     """Padded columns longer than one LDS tile (20480 values) split as
-    Py = P1 P2 with P2 the largest divisor of Py within a tile."""
+    Py = P1 P2, P2 a divisor within a tile (a specialised length if any)."""
     p = lp.Plan(*shape)
     py = p.padding[0]
     assert py > lp.MAX_COLUMN_TILE and py <= lp.MAX_PY
     p1, p2 = p.column_split
     assert p1 * p2 == py and p1 >= 2
-    assert p2 == _largest_divisor_within(py, lp.MAX_COLUMN_TILE)
+    assert p2 == _four_step_p2(py, lp.MAX_COLUMN_TILE)
     # the workspace holds a Py-long scratch column per stored column
     h = p.padding[1] // 2 + 1
     assert p.workspace_bytes >= (h + h % 2) * py * 8

@@ -38,28 +38,30 @@ def sym_kernel(rng, ky, kx):
     return Q[np.abs(np.arange(ky) - cy)][:, np.abs(np.arange(kx) - cx)]
 
 
-CASES = [  # ny, nx, ky, kx, padding (None: default), symmetric kernel, expected (P1, P2)
-    (20000, 4, 1001, 3, None, True, (2, 10800)),          # Py 21600, real-quadrant spectrum form
-    (20000, 5, 1001, 3, None, False, (2, 10800)),         # complex form, odd nx
-    (20000, 4, 1001, 3, (20736, 6), False, (2, 10368)),   # the window bound n + floor(k/2) = 20500
-    (60000, 3, 3001, 3, None, True, (4, 16000)),          # Py 64000
-    (75000, 3, 3001, 1, None, False, (5, 15625)),         # Py 78125 = 5^7
-    (130000, 2, 1001, 1, None, True, (8, 16384)),         # Py 131072 = LP_MAX_PY
+CASES = [  # ny, nx, ky, kx, padding (None: default), symmetric kernel, expected (P1, P2), kernels
+    (20000, 4, 1001, 3, None, True, (4, 5400), "auto"),          # Py 21600, middle in registers (5400)
+    (20000, 5, 1001, 3, None, False, (4, 5400), "auto"),         # complex form, odd nx
+    (20000, 5, 1001, 3, None, False, (4, 5400), "generic"),      # the same split with LDS middle passes
+    (20000, 4, 1001, 3, (20736, 6), False, (8, 2592), "auto"),   # the window bound n + floor(k/2) = 20500
+    (60000, 3, 3001, 3, None, True, (40, 1600), "auto"),         # Py 64000
+    (75000, 3, 3001, 1, None, False, (5, 15625), "auto"),        # Py 78125 = 5^7: no specialised divisor
+    (130000, 2, 1001, 1, None, True, (64, 2048), "auto"),        # Py 131072 = LP_MAX_PY
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"py{c[6][0] * c[6][1]}{'s' if c[5] else 'c'}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"py{c[6][0] * c[6][1]}{'s' if c[5] else 'c'}{c[7][0]}" for c in CASES])
 def test_four_step_full_field(lp, torch, case):
-    ny, nx, ky, kx, pad, sym, split = case
+    ny, nx, ky, kx, pad, sym, split, kern = case
     rng = np.random.default_rng(ny + nx + ky)
     R = rng.random((ny, nx)).astype(np.float32)
     K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
-    plan = lp.make_plan(K, ny, nx, padding=pad)
+    plan = lp.make_plan(K, ny, nx, padding=pad,
+                        kernels=lp.KERNELS_GENERIC if kern == "generic" else lp.KERNELS_AUTO)
     assert plan.column_split == split
     assert plan.form == (lp.FORM_REAL_QUADRANT if sym else lp.FORM_COMPLEX)
     y = plan.convolve(torch.from_numpy(R).cuda())
     torch.cuda.synchronize()
-    check(y.cpu().numpy(), oracle.conv_same(R, K), f"four-step {case[:5]} P={plan.padding}")
+    check(y.cpu().numpy(), oracle.conv_same(R, K), f"four-step {case[:5]} {kern} P={plan.padding}")
 
 
 def test_four_step_adjoint_and_autograd(lp, torch):

@@ -231,6 +231,8 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 2, 4, 1, 1},
     {2400, 160, 15, 16, 10, 2, 4, 1},
     {2400, 160, 16, 15, 10, 2, 4, 1},
+    {13500, 512, 30, 30, 15, 2, 4, 1, 1},
+    {13500, 512, 30, 30, 15, 1, 4, 1, 1},
     {9216, 384, 24, 24, 16, 2, 0, 1},
     {9216, 384, 16, 24, 24, 1, 2, 1},
     {9216, 256, 16, 24, 24, 2, 2, 1},

@@ -169,6 +169,9 @@ def main():
     ap.add_argument("--padding", default="config", choices=["config", "window"],
                     help="config: the workload's padded size; window: the smallest size that still "
                          "gives the exact input-sized window (n + floor(k/2) per axis)")
+    ap.add_argument("--branches", type=int, default=None,
+                    help="batched workload: parallel class branches of the captured graph (1 to 4; "
+                         "default: the autotuner's choice)")
     ap.add_argument("--pad", default=None,
                     help="PY,PX: explicit padded sizes (>= n + floor(k/2), 5-smooth, PX even) instead of --padding")
     ap.add_argument("--variants", default=None,
@@ -355,6 +358,8 @@ def bench_batched(args):
     else:
         from paper_1907_02891_amd import tune
         b, tune_report = tune.autotune_batch(shapes, ids, psfs, xs)
+    if args.branches is not None:
+        b.set_graph_branches(args.branches)
     t_setup = time.perf_counter() - t0
     for _ in range(args.warmup):
         b.convolve(xs, ys)
@@ -373,9 +378,12 @@ def bench_batched(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched-64tiles-3bands-4psf1201", "maps": len(maps), "output_px": npx,
+                   "graph_branches": args.branches if args.branches is not None else next(
+                       (r["graph_branches"] for r in (tune_report or []) if "graph_branches" in r), 2),
                    "classes": [g["padding"] for g in b.groups]},
         "setup_s": {"inputs": round(t_gen, 2), "batch_spectra_and_autotune": round(t_setup, 3)},
-        "autotune": [{"classes": r["classes"], "ms": round(r["ms"], 4)} for r in (tune_report or [])],
+        "autotune": [{"classes": r["classes"], "ms": round(r["ms"], 4)} if "classes" in r else r
+                     for r in (tune_report or [])],
     }
     if not args.no_cpu:
         import oracle

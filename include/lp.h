@@ -370,6 +370,13 @@ int lp_batch_set_output_rows(lp_batch *batch, int tile, int64_t first, int64_t c
 /* Graph replay (default) or direct launches (enable = 0). */
 int lp_batch_use_graph(lp_batch *batch, int enable);
 
+/* Parallel branches of the captured graph (1 to 4, default 2): the padding
+ * classes use disjoint intermediates and spectra, so class g's three stages
+ * are captured on branch g mod n, forked from and joined back into the
+ * bound stream; the runtime may then run classes side by side.  Invalidates
+ * the graph.  Errors: LP_E_INVALID. */
+int lp_batch_set_graph_branches(lp_batch *batch, int n);
+
 /* Classes: count; info for class g: {Py, Px, maps, row variants, column
  * variants, largest map row count} (up to n values); the class of map t. */
 int lp_batch_group_count(const lp_batch *batch);

@@ -1114,6 +1114,12 @@ struct lp_batch {
     bool bound = false, spectra = false;
     bool use_graph = true, graph_ok = false, tables_dirty = true;
     hipStream_t cap = nullptr;
+    // graph branches: classes are independent (own intermediates and
+    // spectra), so the captured graph forks them over kBranches streams
+    static constexpr int kBranches = 4;
+    hipStream_t branch[kBranches] = {};
+    hipEvent_t fork = nullptr, join[kBranches] = {};
+    int branches = 2;  // measured best on the 64-tile workload (1: one linear chain)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const float *> last_in;
@@ -1166,10 +1172,13 @@ int batch_upload_group_tables(lp_batch *b, lp_batch::Group &g)
 }
 
 // Enqueue every launch of one batched call on stream s.
-hipError_t batch_launch_all(lp_batch *b, hipStream_t s)
+// streams[g % nstreams] carries class g (all three of its stages)
+hipError_t batch_launch_all(lp_batch *b, const hipStream_t *streams, int nstreams)
 {
     hipError_t e = hipSuccess;
+    int gi = 0;
     for (auto &g : b->groups) {
+        const hipStream_t s = streams[gi++ % nstreams];
         const float2 *twr = reinterpret_cast<const float2 *>(b->ws + g.off_twr);
         const float2 *twc = reinterpret_cast<const float2 *>(b->ws + g.off_twc);
         lp::RowRegArgs rr{};
@@ -1199,6 +1208,33 @@ hipError_t batch_launch_all(lp_batch *b, hipStream_t s)
         }
     }
     return e;
+}
+
+// The launch sequence under capture on b->cap: with several branches, fork
+// (an event on cap that every branch stream waits for), classes round-robin
+// over the branches, join (cap waits for an event on each branch), so the
+// graph holds independent per-class chains.
+hipError_t batch_capture_all(lp_batch *b)
+{
+    const int nb = std::min<int>(b->branches, static_cast<int>(b->groups.size()));
+    if (nb <= 1) return batch_launch_all(b, &b->cap, 1);
+    hipError_t e;
+    for (int i = 0; i < nb; ++i) {
+        if (!b->branch[i] && (e = hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking)) != hipSuccess) return e;
+        if (!b->join[i] && (e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    if (!b->fork && (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventRecord(b->fork, b->cap)) != hipSuccess) return e;
+    for (int i = 0; i < nb; ++i)
+        if ((e = hipStreamWaitEvent(b->branch[i], b->fork, 0)) != hipSuccess) return e;
+    const hipError_t le = batch_launch_all(b, b->branch, nb);
+    // join every branch that joined the capture, also after a failed launch,
+    // so the capture can end
+    for (int i = 0; i < nb; ++i) {
+        if ((e = hipEventRecord(b->join[i], b->branch[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(b->cap, b->join[i], 0)) != hipSuccess) return e;
+    }
+    return le;
 }
 
 }  // namespace
@@ -1395,6 +1431,11 @@ void lp_batch_destroy(lp_batch *b)
     if (!b) return;
     batch_destroy_graph(b);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int i = 0; i < lp_batch::kBranches; ++i) {
+        if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
 }
 
@@ -1533,14 +1574,14 @@ int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const 
         b->tables_dirty = false;
     }
     if (!b->use_graph) {
-        if ((e = batch_launch_all(b, b->stream)) != hipSuccess) return fail_hip(e, "batched launch");
+        if ((e = batch_launch_all(b, &b->stream, 1)) != hipSuccess) return fail_hip(e, "batched launch");
         return LP_OK;
     }
     if (!b->graph_ok) {
         if (!b->cap && (e = hipStreamCreate(&b->cap)) != hipSuccess) return fail_hip(e, "capture stream");
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return fail_hip(e, "graph capture");
-        const hipError_t le = batch_launch_all(b, b->cap);
+        const hipError_t le = batch_capture_all(b);
         hipGraph_t gph = nullptr;
         e = hipStreamEndCapture(b->cap, &gph);
         if (le != hipSuccess) {
@@ -1604,6 +1645,20 @@ int lp_batch_use_graph(lp_batch *b, int enable)
     clear_error();
     if (!b) return fail(LP_E_INVALID, "null batch");
     b->use_graph = enable != 0;
+    return LP_OK;
+}
+
+int lp_batch_set_graph_branches(lp_batch *b, int n)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (n < 1 || n > lp_batch::kBranches)
+        return fail(LP_E_INVALID, "graph branches %d outside [1, %d]", n, lp_batch::kBranches);
+    if (b->branches != n) {
+        b->branches = n;
+        batch_destroy_graph(b);
+        b->graph_ok = false;
+    }
     return LP_OK;
 }
 

@@ -105,6 +105,7 @@ _SIGS = {
     "lp_batch_group_info": ([_vp, ctypes.c_int, _i64p, ctypes.c_int], ctypes.c_int),
     "lp_batch_tile_group": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_batch_set_variant": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "lp_batch_set_graph_branches": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_batch_get_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -444,6 +445,10 @@ class Batch:
 
     def set_variant(self, g, stage, k):
         _check(_lib.lp_batch_set_variant(self._b, int(g), int(stage), int(k)))
+
+    def set_graph_branches(self, n):
+        """Classes captured on n parallel graph branches (1 to 4)."""
+        _check(_lib.lp_batch_set_graph_branches(self._b, int(n)))
 
     def variant(self, g, stage):
         return int(_lib.lp_batch_get_variant(self._b, int(g), int(stage)))

@@ -201,4 +201,15 @@ def autotune_batch(shapes, psf_ids, psfs, maps, *, pitch_km=0.5, reps=3, warmup=
         else:
             b.close()
         torch.cuda.empty_cache()
-    return best[1], report
+    # parallel class branches of the captured graph, on the chosen classes
+    b = best[1]
+    times = {}
+    for n in (1, 2, 3, 4):
+        b.set_graph_branches(n)
+        times[n] = _time_batch(b, maps, ys, reps, warmup)
+        if verbose:
+            print(f"tune batch: {n} graph branches, {times[n]:.3f} ms", flush=True)
+    n_best = min(times, key=times.get)
+    b.set_graph_branches(n_best)
+    report.append({"graph_branches_ms": {str(k): v for k, v in times.items()}, "graph_branches": n_best})
+    return b, report

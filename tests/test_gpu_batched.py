@@ -76,6 +76,30 @@ def test_batch_parity_and_graph(lp, torch):
         assert np.array_equal(g2[t], d[t])
 
 
+@pytest.mark.parametrize("branches", [1, 2, 3])
+def test_graph_branches_match_direct(lp, torch, branches):
+    """The captured graph with 1 to 4 parallel class branches gives the
+    direct launches' results bitwise, over replays with eager work between."""
+    shapes, ids, psfs, maps = small_batch()
+    b = lp.Batch(shapes, ids, [p.shape for p in psfs]).bind()
+    b.set_kernels(psfs)
+    b.set_graph_branches(branches)
+    d = lp.Batch(shapes, ids, [p.shape for p in psfs]).bind()
+    d.set_kernels(psfs)
+    d.use_graph(False)
+    xs = [torch.from_numpy(m).cuda() for m in maps]
+    outs = [torch.empty_like(x) for x in xs]
+    for rep in range(3):
+        for x in xs:
+            x.mul_(0.75).add_(0.5)
+        g = [o.cpu().numpy() for o in b.convolve(xs, outs)]
+        r = [o.cpu().numpy() for o in d.convolve(xs)]
+        for t in range(len(xs)):
+            assert np.array_equal(g[t], r[t]), (branches, rep, t)
+    with pytest.raises(lp.LPError):
+        b.set_graph_branches(5)
+
+
 def test_batch_in_place(lp, torch):
     shapes, ids, psfs, maps = small_batch()
     b = lp.Batch(shapes, ids, [p.shape for p in psfs]).bind()

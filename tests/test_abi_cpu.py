@@ -350,3 +350,17 @@ def test_window_padding_bounds():
     # a map whose n + k - 1 exceeds the maximum still gets a plan
     big = lp.Plan(19000, 100, 2001, 3)
     assert big.padding[0] >= 19000 + 1000 and big.padding[0] <= lp.MAX_PY
+
+
+def test_graph_branches_and_column_split_errors():
+    lib = lp.raw()
+    b = lp.Batch([(600, 700), (100, 100)], [0, 0], [(101, 101)])
+    for n in (0, 5, -1):
+        assert lib.lp_batch_set_graph_branches(b._b, n) == lp.LP_E_INVALID
+    for n in (1, 2, 3, 4):
+        assert lib.lp_batch_set_graph_branches(b._b, n) == lp.LP_OK
+    assert lib.lp_batch_set_graph_branches(None, 2) == lp.LP_E_INVALID
+    p = lp.Plan(20000, 4, 1001, 3)
+    one = ctypes.c_int64()
+    assert lib.lp_plan_column_split(p._p, None, ctypes.byref(one)) == lp.LP_E_INVALID
+    assert lib.lp_plan_column_split(None, ctypes.byref(one), ctypes.byref(one)) == lp.LP_E_INVALID

@@ -478,4 +478,26 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
     return x * q + (x < r ? x : r) + j;
 }
 
+// Copy of elements 0..total-1, element e = tid + k nt to thread tid: CH of a
+// thread's elements are loaded (load(e)) before any is stored (store(e, x)),
+// so that its global loads are in flight together rather than one load,
+// wait and store per element.
+template <int CH, class Load, class Store>
+__device__ __forceinline__ void staged_copy(int total, int tid, int nt, Load load, Store store)
+{
+    for (int e0 = tid; e0 < total; e0 += CH * nt) {
+        float2 x[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = e0 + k * nt;
+            x[k] = (e < total) ? load(e) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int e = e0 + k * nt;
+            if (e < total) store(e, x[k]);
+        }
+    }
+}
+
 }  // namespace lp

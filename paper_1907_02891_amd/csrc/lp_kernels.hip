@@ -41,15 +41,15 @@ __global__ void __launch_bounds__(1024) k_rows_r2c(const float *__restrict__ R,
     for (int b = 0; b < B; ++b) {
         const int row = row0 + b;
         const float *src = R + static_cast<int64_t>(row) * a.nx;
-        for (int n = tid; n < m; n += nt) {
+        staged_copy<8>(m, tid, nt, [&](int n) {
             float x0 = 0.f, x1 = 0.f;
             if (row < a.ny) {
                 const int c0 = 2 * n;
                 if (c0 < a.nx) x0 = src[c0];
                 if (c0 + 1 < a.nx) x1 = src[c0 + 1];
             }
-            lds[(n << a.logb) + b] = make_float2(x0, x1);
-        }
+            return make_float2(x0, x1);
+        }, [&](int n, float2 x) { lds[(n << a.logb) + b] = x; });
     }
     __syncthreads();
     lds_fft<false, SPLIT>(lds, a.fx, a.logb, a.tw, tid, nt, a.mf);
@@ -118,8 +118,8 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
             const float2 *src = col + t * a.w_stride;
             const void *kh = static_cast<const char *>(a.kh) + t * a.kh_stride;
             __syncthreads();  // the previous class's products are all read
-            for (int e = tid; e < py; e += nt)
-                lds[e] = (e < ny) ? src[e << lc] : make_float2(0.f, 0.f);
+            staged_copy<8>(py, tid, nt, [&](int e) { return (e < ny) ? src[e << lc] : make_float2(0.f, 0.f); },
+                           [&](int e, float2 x) { lds[e] = x; });
             __syncthreads();
             lds_fft<false, SPLIT>(lds, a.fy, 0, a.tw, opaque_v(tid), nt, a.mf);
             const int t0 = opaque_v(tid);
@@ -136,11 +136,12 @@ __global__ void __launch_bounds__(1024) k_cols_conv(float2 *__restrict__ W, ColA
             if (e < py) lds[e] = acc[q];
         }
     } else {
-        for (int e = tid; e < py; e += nt)
-            lds[e] = (e < ny) ? col[e << lc] : make_float2(0.f, 0.f);
+        staged_copy<8>(py, tid, nt, [&](int e) { return (e < ny) ? col[e << lc] : make_float2(0.f, 0.f); },
+                       [&](int e, float2 x) { lds[e] = x; });
         __syncthreads();
         lds_fft<false, SPLIT>(lds, a.fy, 0, a.tw, tid, nt, a.mf);
-        for (int e = tid; e < py; e += nt) lds[e] = spec(a.kh, e, lds[e]);
+        staged_copy<8>(py, tid, nt, [&](int e) { return spec(a.kh, e, lds[e]); },
+                       [&](int e, float2 x) { lds[e] = x; });
     }
     __syncthreads();
     lds_fft<true, SPLIT>(lds, a.fy, 0, a.tw, tid, nt, a.mf);
@@ -161,18 +162,20 @@ __global__ void __launch_bounds__(1024) k_rows_c2r(const float2 *__restrict__ W,
 
     // Stage X[k], 0 <= k <= M, of B rows (slot (k, b) = k * B + b).
     const int total = a.nblk << (a.logb + a.logc);
-    for (int e = tid; e < total; e += nt) {
+    staged_copy<8>(total, tid, nt, [&](int e) {
         const int c = e & (C - 1);
         const int b = (e >> a.logc) & (B - 1);
         const int kb = e >> (a.logc + a.logb);
         const int k = (kb << a.logc) + c;
         const int row = row0 + b;
-        if (k < a.h) {
-            float2 X = make_float2(0.f, 0.f);
-            if (row < a.ny) X = W[((static_cast<int64_t>(kb) * a.ny + row) << a.logc) + c];
-            lds[(k << a.logb) + b] = X;
-        }
-    }
+        return (k < a.h && row < a.ny) ? W[((static_cast<int64_t>(kb) * a.ny + row) << a.logc) + c]
+                                       : make_float2(0.f, 0.f);
+    }, [&](int e, float2 x) {
+        const int c = e & (C - 1);
+        const int b = (e >> a.logc) & (B - 1);
+        const int k = ((e >> (a.logc + a.logb)) << a.logc) + c;
+        if (k < a.h) lds[(k << a.logb) + b] = x;
+    });
     __syncthreads();
 
     // Z[k] = (X[k] + conj X[M-k]) + i w^-k (X[k] - conj X[M-k]), 0 <= k < M
@@ -776,7 +779,8 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_long_mid_reg(Lon
     using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
     const int tt = threadIdx.x;
     const bool act = tt < TF;
-    const int v = blockIdx.x, k1 = blockIdx.y;
+    // the two columns of an interleaved group on one XCD (shared spectrum lines)
+    const int v = xcd_tile(blockIdx.x, gridDim.x), k1 = blockIdx.y;
     float2 *t = a.T + static_cast<int64_t>(v) * a.py + static_cast<int64_t>(k1) * N;
     float2 x0[F0::S][R0];
     if (act) {

@@ -25,7 +25,12 @@
 // The outer transforms are the LDS Stockham passes of the generic kernels
 // (radix 2/3/4/5/8, FP32).  HBM traffic is three passes over a Py-long
 // scratch column instead of one over the ny stored rows: this path exists
-// for sizes the single-tile kernels cannot take, not for speed.
+// for sizes the single-tile kernels cannot take, not for speed.  The two
+// columns of an interleaved pair share every line of the intermediate and of
+// the spectrum, so all three kernels place them on one XCD (xcd_tile): the
+// second of the two reads then hits that XCD's L2 and the halves of a line
+// written by the inverse kernel meet there, instead of each line crossing
+// HBM twice.
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.h"
@@ -38,18 +43,16 @@ __global__ void __launch_bounds__(1024) k_long_fwd(const float2 *__restrict__ W,
 {
     extern __shared__ float2 lds[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int v = blockIdx.x, B = 1 << a.logb, n2b = blockIdx.y << a.logb;
+    const int v = xcd_tile(blockIdx.x, gridDim.x), B = 1 << a.logb, n2b = blockIdx.y << a.logb;
     const int lc = a.lc, cm = (1 << lc) - 1;
     const float2 *col = W + ((static_cast<int64_t>(v >> lc) * a.ny) << lc) + (v & cm);
     // slot (n1, b) = n1 B + b holds x[P2 n1 + n2b + b]
     const int total = a.p1 << a.logb;
-    for (int e = tid; e < total; e += nt) {
+    staged_copy<8>(total, tid, nt, [&](int e) {
         const int b = e & (B - 1), n1 = e >> a.logb, n2 = n2b + b;
         const int64_t n = static_cast<int64_t>(a.p2) * n1 + n2;
-        float2 x = make_float2(0.f, 0.f);
-        if (n2 < a.p2 && n < a.ny) x = col[n << lc];
-        lds[e] = x;
-    }
+        return (n2 < a.p2 && n < a.ny) ? col[n << lc] : make_float2(0.f, 0.f);
+    }, [&](int e, float2 x) { lds[e] = x; });
     __syncthreads();
     lds_fft<false>(lds, a.f1, a.logb, a.tw1, tid, nt);
     float2 *t = a.T + static_cast<int64_t>(v) * a.py;
@@ -65,25 +68,24 @@ __global__ void __launch_bounds__(1024) k_long_mid(LongArgs a)
 {
     extern __shared__ float2 lds[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int v = blockIdx.x, k1 = blockIdx.y;
+    const int v = xcd_tile(blockIdx.x, gridDim.x), k1 = blockIdx.y;
     float2 *t = a.T + static_cast<int64_t>(v) * a.py + static_cast<int64_t>(k1) * a.p2;
-    for (int n2 = tid; n2 < a.p2; n2 += nt) lds[n2] = t[n2];
+    staged_copy<8>(a.p2, tid, nt, [&](int n2) { return t[n2]; }, [&](int n2, float2 x) { lds[n2] = x; });
     __syncthreads();
     lds_fft<false>(lds, a.f2, 0, a.tw2, tid, nt);
     // Eq. 9: X[k1 + P1 k2] times the spectrum, stored row k1 P2 + k2
     const int lc = a.lc, cm = (1 << lc) - 1;
     const int64_t base = ((static_cast<int64_t>(v >> lc) * a.py + static_cast<int64_t>(k1) * a.p2) << lc) + (v & cm);
-    for (int k2 = tid; k2 < a.p2; k2 += nt) {
+    staged_copy<8>(a.p2, tid, nt, [&](int k2) {
         const int64_t idx = base + (static_cast<int64_t>(k2) << lc);
-        float2 x = lds[k2];
+        const float2 x = lds[k2];
         if constexpr (FORM == 1) {
-            x = cscale(x, static_cast<const float *>(a.kh)[idx]);
+            return cscale(x, static_cast<const float *>(a.kh)[idx]);
         } else {
             const float2 k = static_cast<const float2 *>(a.kh)[idx];
-            x = CONJ ? cmulc(x, k) : cmul(x, k);
+            return CONJ ? cmulc(x, k) : cmul(x, k);
         }
-        lds[k2] = x;
-    }
+    }, [&](int k2, float2 x) { lds[k2] = x; });
     __syncthreads();
     lds_fft<true>(lds, a.f2, 0, a.tw2, tid, nt);
     for (int n2 = tid; n2 < a.p2; n2 += nt) t[n2] = cmulc(lds[n2], a.twq[n2 * k1]);
@@ -93,13 +95,13 @@ __global__ void __launch_bounds__(1024) k_long_inv(float2 *__restrict__ W, LongA
 {
     extern __shared__ float2 lds[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int v = blockIdx.x, B = 1 << a.logb, n2b = blockIdx.y << a.logb;
+    const int v = xcd_tile(blockIdx.x, gridDim.x), B = 1 << a.logb, n2b = blockIdx.y << a.logb;
     const float2 *t = a.T + static_cast<int64_t>(v) * a.py;
     const int total = a.p1 << a.logb;
-    for (int e = tid; e < total; e += nt) {
+    staged_copy<8>(total, tid, nt, [&](int e) {
         const int b = e & (B - 1), k1 = e >> a.logb, n2 = n2b + b;
-        lds[e] = (n2 < a.p2) ? t[static_cast<int64_t>(k1) * a.p2 + n2] : make_float2(0.f, 0.f);
-    }
+        return (n2 < a.p2) ? t[static_cast<int64_t>(k1) * a.p2 + n2] : make_float2(0.f, 0.f);
+    }, [&](int e, float2 x) { lds[e] = x; });
     __syncthreads();
     lds_fft<true>(lds, a.f1, a.logb, a.tw1, tid, nt);
     const int lc = a.lc, cm = (1 << lc) - 1;

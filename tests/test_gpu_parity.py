@@ -349,11 +349,12 @@ def test_window_padding_full_field(lp, torch, case):
 
 # ---------------------------------------------------------- maximum sizes --
 
-MAX_CASES = [  # ny, nx, ky, kx, padding: the longest column and the longest row a plan accepts
-    (19000, 4, 1481, 3, (20480, 6)),     # Py = LP_MAX_PY: one column fills the 160 KB of LDS
+MAX_CASES = [  # ny, nx, ky, kx, padding: the longest single-tile column and the longest row
+    (19000, 4, 1481, 3, (20480, 6)),     # Py = 20480: one column fills the 160 KB of LDS
     (3, 39000, 3, 1501, (4, 40500)),     # Px = 40500: largest even 5-smooth length <= LP_MAX_PX
-    (19500, 4, 1481, 3, None),           # n + k - 1 > LP_MAX_PY: default falls back to n + floor(k/2)
+    (19500, 4, 1481, 3, None),           # n + k - 1 = 20980 > 20480: the default 21600 takes four-step columns
 ]
+# (the longest four-step column, Py = LP_MAX_PY = 131072, is a case of test_gpu_long.py)
 
 
 @pytest.mark.parametrize("case", MAX_CASES, ids=["py20480", "px40500", "py-default"])
@@ -366,5 +367,7 @@ def test_maximum_sizes_full_field(lp, torch, case):
     if pad is not None:
         assert plan.padding == pad
     assert plan.padding[0] <= lp.MAX_PY and plan.padding[1] <= lp.MAX_PX
+    if pad is None:
+        assert plan.padding[0] == 21600 and plan.column_split[0] > 1
     y = plan.convolve(torch.from_numpy(R).cuda()).cpu().numpy()
     assert_parity(y, oracle.conv_same(R, K), label=f"max size {case} P={plan.padding}")

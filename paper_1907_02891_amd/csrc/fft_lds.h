@@ -478,6 +478,16 @@ __device__ __forceinline__ int xcd_tile(int b, int G)
     return x * q + (x < r ? x : r) + j;
 }
 
+// Tile of workgroup b among the tiles of B rows that hold a kept row
+// [keep0, keep1), dealt over the XCDs as xcd_tile deals a whole grid; -1
+// past the last such tile.  Dealing the whole grid would leave idle the XCDs
+// whose contiguous share of tiles lies outside a narrow kept window.
+__device__ __forceinline__ int kept_tile(int b, int ntiles, int B, int keep0, int keep1)
+{
+    const int k0 = keep0 / B, k1 = min(ntiles, (keep1 + B - 1) / B);
+    return b < k1 - k0 ? k0 + xcd_tile(b, k1 - k0) : -1;
+}
+
 // Copy of elements 0..total-1, element e = tid + k nt to thread tid: CH of a
 // thread's elements are loaded (load(e)) before any is stored (store(e, x)),
 // so that its global loads are in flight together rather than one load,

@@ -1309,8 +1309,9 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         }
     };
 
-    const int t0 = xcd_tile(blockIdx.x, G);
-    if (t0 >= ntiles) return;
+    // one tile per workgroup: only tiles with a kept row are dealt out
+    const int t0 = (TPW == 1) ? kept_tile(blockIdx.x, ntiles, B, a.keep0, a.keep1) : xcd_tile(blockIdx.x, G);
+    if (t0 < 0 || t0 >= ntiles) return;
     const int tt0 = tid0 / B, b0 = tid0 % B;
     if constexpr (TPW == 1) {
         // a tile with no row to keep does nothing (uniform over the workgroup)
@@ -1502,8 +1503,9 @@ k_rows_c2r_half(const float2 *__restrict__ W, float *__restrict__ Sm, RowRegArgs
         a.keep1 = it.keep1;
     }
     const int ntiles = (a.ny + B - 1) / B;
-    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
-    if (t0 >= ntiles) return;
+    // only tiles with a kept row are dealt out
+    const int t0 = kept_tile(blockIdx.x, ntiles, B, a.keep0, a.keep1);
+    if (t0 < 0) return;
     // a tile with no row to keep does nothing (uniform over the workgroup)
     if (t0 * B >= a.keep1 || (t0 + 1) * B <= a.keep0) return;
     const int tt = threadIdx.x / B, b = threadIdx.x % B;

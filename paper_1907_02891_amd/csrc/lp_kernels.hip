@@ -1151,8 +1151,10 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
         }
     };
 
-    const int t0 = xcd_tile(blockIdx.x, G);
-    if (t0 >= ntiles) return;
+    // one tile per workgroup: the item's own tiles are dealt out (in a batch
+    // the grid spans the largest item)
+    const int t0 = (TPW == 1) ? kept_tile(blockIdx.x, ntiles, B, 0, a.ny) : xcd_tile(blockIdx.x, G);
+    if (t0 < 0 || t0 >= ntiles) return;
     const int tt0 = tid0 / B, b0 = tid0 % B;
     if constexpr (TPW == 1) {
         float2 x0[F0::S][R0];
@@ -1388,8 +1390,9 @@ k_rows_r2c_half(const float *__restrict__ Rm, float2 *__restrict__ W, RowRegArgs
         a.nx = it.nx;
     }
     const int ntiles = (a.ny + B - 1) / B;
-    const int t0 = xcd_tile(blockIdx.x, gridDim.x);
-    if (t0 >= ntiles) return;
+    // the item's own tiles are dealt out (in a batch the grid spans the largest item)
+    const int t0 = kept_tile(blockIdx.x, ntiles, B, 0, a.ny);
+    if (t0 < 0) return;
     const int tt = threadIdx.x / B, b = threadIdx.x % B;
     const int row = t0 * B + b;
     const bool rv = row < a.ny;

@@ -188,3 +188,31 @@ def test_window_padding_slab(lp, torch, case):
     b.set_output_rows(0, k0 + 10, k1 - k0 - 20)  # a narrower window fits the class
     out2 = b.convolve([torch.from_numpy(R).cuda()])[0]
     assert np.array_equal(out2.cpu().numpy(), out.cpu().numpy()[10:-10])
+
+
+def test_uneven_maps_and_windows_in_one_class(lp, torch):
+    """Maps of very different heights in one padding class: the grid spans
+    the tallest map, and each map's own tiles (in the inverse rows, only
+    those that hold kept rows) are dealt over the XCDs.  Output-row windows
+    at the top, in the middle and at the bottom of maps; every kept row
+    equals the oracle's, and so does every whole map."""
+    rng = np.random.default_rng(404)
+    K = rng.random((61, 41))
+    shapes = [(1170, 300), (500, 300), (1100, 300), (1100, 300), (800, 300), (1, 300)]
+    windows = {2: (0, 100), 3: (450, 37), 4: (700, 100)}
+    maps = [rng.random(s).astype(np.float32) for s in shapes]
+    b = lp.Batch(shapes, [0] * len(shapes), [K.shape])
+    for t, (k0, n) in windows.items():
+        b.set_output_rows(t, k0, n)
+    b.bind()
+    b.set_kernels([K])
+    groups, g = b.groups, b.tile_group(0)
+    assert [b.tile_group(t) for t in range(5)] == [g] * 5, groups   # the one-row map has a class of its own
+    assert groups[g]["padding"] == (1200, 512) and groups[g]["maps"] == 5 and groups[g]["max_ny"] == 1170, groups
+    outs = b.convolve([torch.from_numpy(m).cuda() for m in maps])
+    torch.cuda.synchronize()
+    for t, (m, o) in enumerate(zip(maps, outs)):
+        k0, n = windows.get(t, (0, shapes[t][0]))
+        got = o.cpu().numpy()
+        assert got.shape == (n, shapes[t][1])
+        check(got, oracle.conv_same(m, K)[k0:k0 + n], f"uneven map {t} {shapes[t]} rows [{k0}, {k0 + n})")

@@ -187,12 +187,17 @@ int lp_convolve_classes(lp_plan *plan, const float *const *radiance, float *out)
  * LP_E_INVALID for cls outside [0, T). */
 int lp_adjoint_class(lp_plan *plan, int cls, const float *grad_out, float *grad_in);
 
-/* Per-stage timing with HIP events on the bound stream.  enable != 0 starts
- * recording events around each of the three stages of every lp_convolve /
- * lp_adjoint call (up to 1024 calls are kept); lp_plan_stage_ms synchronises
- * on the last event, writes the summed milliseconds of stage s (0: rows
- * forward, 1: columns, 2: rows inverse) to ms[s] for s < n, the number of
- * calls to *calls, and clears the record. */
+/* Per-stage timing with HIP events on the bound stream.  enable = N > 0
+ * starts recording events around each of the three stages of every N-th
+ * call that runs the path (lp_convolve, lp_adjoint, lp_convolve_classes,
+ * lp_adjoint_class), counting from the next one (up to 1024 recorded calls
+ * are kept); 0 stops; N < 0 is
+ * LP_E_INVALID.  The four events of a recorded call add some microseconds to
+ * it, so a caller timing many calls can sample them with N > 1.
+ * lp_plan_stage_ms synchronises on the last event, writes the summed
+ * milliseconds of stage s (0: rows forward, 1: columns, 2: rows inverse) of
+ * the recorded calls to ms[s] for s < n, their number to *calls, and clears
+ * the record. */
 int lp_plan_timing(lp_plan *plan, int enable);
 int lp_plan_stage_ms(lp_plan *plan, double *ms, int n, int *calls);
 

@@ -238,8 +238,9 @@ struct lp_plan {
     hipStream_t stream = nullptr;
     bool bound = false;
     int form = LP_FORM_NONE;
-    // timing
-    bool timing = false;
+    // timing: events around the stages of every timing_every-th call (0: off)
+    int timing_every = 0;
+    int64_t timing_seen = 0;
     std::vector<hipEvent_t> ev;
     int ev_calls = 0;
 };
@@ -497,7 +498,11 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     if (p->form == LP_FORM_NONE) return fail(LP_E_STATE, "%s: kernel spectrum not computed", who);
     const bool sum = nin > 1;
     hipError_t e;
-    const bool rec = p->timing && p->ev_calls < kMaxTimedCalls;
+    bool rec = false;
+    if (p->timing_every > 0) {
+        rec = p->timing_seen % p->timing_every == 0 && p->ev_calls < kMaxTimedCalls;
+        ++p->timing_seen;
+    }
     hipEvent_t *ev = rec ? &p->ev[4 * p->ev_calls] : nullptr;
     if (rec && (e = hipEventRecord(ev[0], p->stream)) != hipSuccess) return fail_hip(e, who);
     float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
@@ -1035,6 +1040,7 @@ int lp_plan_timing(lp_plan *p, int enable)
 {
     clear_error();
     if (!p) return fail(LP_E_INVALID, "null plan");
+    if (enable < 0) return fail(LP_E_INVALID, "timing interval %d < 0", enable);
     if (enable && p->ev.empty()) {
         p->ev.resize(4 * kMaxTimedCalls);
         for (auto &e : p->ev) {
@@ -1045,7 +1051,8 @@ int lp_plan_timing(lp_plan *p, int enable)
             }
         }
     }
-    p->timing = enable != 0;
+    p->timing_every = enable;
+    p->timing_seen = 0;
     p->ev_calls = 0;
     return LP_OK;
 }

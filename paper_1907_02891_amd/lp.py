@@ -332,8 +332,10 @@ class Plan:
         return {"radices": (v[0], v[1], v[2]), "threads": v[3], "per_group": v[4],
                 "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8])}
 
-    def timing(self, enable=True):
-        _check(_lib.lp_plan_timing(self._p, int(bool(enable))))
+    def timing(self, enable=True, every=1):
+        """Stage events on every `every`-th call from the next one
+        (lp_plan_timing); enable=False stops."""
+        _check(_lib.lp_plan_timing(self._p, int(every) if enable else 0))
 
     def stage_ms(self):
         """(per-stage summed ms [rows fwd, columns, rows inv], calls)."""

@@ -364,3 +364,13 @@ def test_graph_branches_and_column_split_errors():
     one = ctypes.c_int64()
     assert lib.lp_plan_column_split(p._p, None, ctypes.byref(one)) == lp.LP_E_INVALID
     assert lib.lp_plan_column_split(None, ctypes.byref(one), ctypes.byref(one)) == lp.LP_E_INVALID
+
+
+def test_timing_interval_errors():
+    """lp_plan_timing takes an interval N >= 0 (0 stops; no events are made
+    for 0); a negative interval or a null plan is refused."""
+    lib = lp.raw()
+    p = lp.Plan(300, 200, 31, 31)
+    assert lib.lp_plan_timing(p._p, -1) == lp.LP_E_INVALID
+    assert lib.lp_plan_timing(p._p, 0) == lp.LP_OK
+    assert lib.lp_plan_timing(None, 1) == lp.LP_E_INVALID

@@ -54,6 +54,7 @@ def _load():
                                            _c_dbl_p, _i64, _c_i64_p, _i64,
                                            _c_dbl_p],
         "orc_num_threads": [],
+        "orc_set_num_threads": [ctypes.c_int],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -80,6 +81,12 @@ def _check(rc, name):
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Threads for the oracle's OpenMP loops from now on; returns the number
+    in effect."""
+    return int(_load().orc_set_num_threads(int(n)))
 
 
 def conv_full(R, K):

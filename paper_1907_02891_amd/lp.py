@@ -141,6 +141,28 @@ def raw():
     return _lib
 
 
+def _ordered(bound, tensors, launch):
+    """Run `launch` (which enqueues on the plan's bound stream) ordered with
+    torch's current stream: when the two differ, the bound stream first waits
+    for the work already queued on the current one (which may still be
+    writing the inputs), the current stream then waits for the bound one (so
+    the outputs are complete for whatever the caller queues next), and every
+    tensor is marked as used on the bound stream so that the caching
+    allocator does not hand its memory out again before that stream is done
+    with it."""
+    import torch
+    cur = torch.cuda.current_stream(tensors[0].device)
+    if bound is None or cur == bound:
+        return launch()
+    bound.wait_stream(cur)
+    try:
+        return launch()
+    finally:
+        cur.wait_stream(bound)
+        for t in tensors:
+            t.record_stream(bound)
+
+
 def _stream_ptr(stream):
     import torch
     s = torch.cuda.current_stream() if stream is None else stream
@@ -265,17 +287,20 @@ class Plan:
         return out
 
     def convolve(self, radiance, out=None):
-        """S = K (*) R, "same" size, on the bound stream (lp_convolve)."""
+        """S = K (*) R, "same" size, on the bound stream (lp_convolve),
+        ordered with torch's current stream."""
         out = self._io(radiance, out)
-        _check(_lib.lp_convolve(self._p, ctypes.c_void_p(radiance.data_ptr()),
-                                ctypes.c_void_p(out.data_ptr())))
+        _ordered(self.stream, [radiance, out],
+                 lambda: _check(_lib.lp_convolve(self._p, ctypes.c_void_p(radiance.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()))))
         return out
 
     def adjoint(self, grad_out, out=None):
-        """Transposed operator (lp_adjoint)."""
+        """Transposed operator (lp_adjoint), ordered as convolve."""
         out = self._io(grad_out, out)
-        _check(_lib.lp_adjoint(self._p, ctypes.c_void_p(grad_out.data_ptr()),
-                               ctypes.c_void_p(out.data_ptr())))
+        _ordered(self.stream, [grad_out, out],
+                 lambda: _check(_lib.lp_adjoint(self._p, ctypes.c_void_p(grad_out.data_ptr()),
+                                                ctypes.c_void_p(out.data_ptr()))))
         return out
 
     def convolve_classes(self, maps, out=None):
@@ -286,14 +311,16 @@ class Plan:
         for m in maps[1:]:
             self._io(m, out)
         ptrs = (_vp * len(maps))(*[m.data_ptr() for m in maps])
-        _check(_lib.lp_convolve_classes(self._p, ptrs, ctypes.c_void_p(out.data_ptr())))
+        _ordered(self.stream, list(maps) + [out],
+                 lambda: _check(_lib.lp_convolve_classes(self._p, ptrs, ctypes.c_void_p(out.data_ptr()))))
         return out
 
     def adjoint_class(self, cls, grad_out, out=None):
         """C_cls^T grad_out (lp_adjoint_class)."""
         out = self._io(grad_out, out)
-        _check(_lib.lp_adjoint_class(self._p, int(cls), ctypes.c_void_p(grad_out.data_ptr()),
-                                     ctypes.c_void_p(out.data_ptr())))
+        _ordered(self.stream, [grad_out, out],
+                 lambda: _check(_lib.lp_adjoint_class(self._p, int(cls), ctypes.c_void_p(grad_out.data_ptr()),
+                                                      ctypes.c_void_p(out.data_ptr()))))
         return out
 
     def set_kernels(self, which):
@@ -370,6 +397,7 @@ class Batch:
         self.shapes = [(int(a), int(b)) for a, b in shapes]
         self.psf_shapes = [tuple(p) for p in psf_shapes]
         self.workspace = None
+        self.stream = None
 
     def close(self):
         if getattr(self, "_b", None) and _lib is not None:
@@ -426,7 +454,8 @@ class Batch:
         n = len(self.shapes)
         ins = (_vp * n)(*[m.data_ptr() for m in maps])
         ous = (_vp * n)(*[o.data_ptr() for o in outs])
-        _check(_lib.lp_convolve_batched(self._b, ins, ous))
+        _ordered(self.stream, list(maps) + list(outs),
+                 lambda: _check(_lib.lp_convolve_batched(self._b, ins, ous)))
         return outs
 
     def use_graph(self, enable=True):

@@ -182,6 +182,33 @@ def test_deterministic_and_in_place(lp, torch):
     assert np.array_equal(y.cpu().numpy(), a)
 
 
+def test_side_stream_ordering(lp, torch):
+    """A plan bound to the default stream, called under a side stream that
+    has just written its input and reads the output right after: the binding
+    orders the bound stream after the side stream and back, so the result is
+    the oracle's (and the same bits as on the bound stream)."""
+    R, K = synth.small_inputs()
+    plan = lp.make_plan(K, *R.shape, padding=(512, 512))
+    x0 = torch.from_numpy(R).cuda()
+    want = plan.convolve(x0).cpu().numpy()
+    side = torch.cuda.Stream()
+    for _ in range(3):
+        with torch.cuda.stream(side):
+            # a long chain of queued work that writes the input on the side stream
+            x = torch.zeros_like(x0)
+            for _ in range(50):
+                x.add_(x0)
+            x.mul_(1.0 / 50.0)
+            y = plan.convolve(x)
+            z = y * 2.0          # consumer queued on the side stream
+            del x                # freed while the bound stream may still hold it
+        side.synchronize()
+        torch.cuda.synchronize()
+        assert_parity(y.cpu().numpy(), oracle.conv_same(R, K), label="side stream")
+        np.testing.assert_array_equal(z.cpu().numpy(), 2.0 * y.cpu().numpy())
+    np.testing.assert_allclose(y.cpu().numpy(), want, rtol=1e-6, atol=1e-6 * np.abs(want).max())
+
+
 def test_linearity_and_sum(lp, torch):
     rng = np.random.default_rng(8)
     ny, nx, ky, kx = 90, 80, 21, 21

@@ -99,16 +99,86 @@ def test_band_kernel_geometry():
     np.testing.assert_allclose(K60[:, 4], K0_eq[:, 4], rtol=1e-14)
 
 
+def _alr_constants():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "eq12_13_alr.txt"))
+            if l.strip() and not l.startswith("#")]
+    return {k: float(v) for k, v in rows}
+
+
 def test_alr_kernel_eq12_13():
-    half, pitch = 40, 0.5
+    """Eqs. 12-13 at the points where they reduce to closed forms, with the
+    constants printed in the paper (fixture): d = 1 km, where ln d = 0 so
+    K = c whatever alpha is; d = d0 = 350 km, where alpha = 2.3 exactly; the
+    d -> 0 limit (alpha -> 0, K -> c); the cut at the 300 km validity range."""
+    g = _alr_constants()
+    c = 1.0 / g["c_denominator"]
+    assert synth.ALR_C == c
+    pitch = 0.5
+    half = int(round(g["d0_km"] / pitch))          # the grid reaches d = 350 km on each axis
     K = synth.psf_alr(half, pitch, radius_km=None)
-    assert K[half, half] == synth.ALR_C            # finite limit at d -> 0
-    # alpha(350 km) = 2.3 exactly: K(350) = c 350^-2.3
-    d = 350.0
-    assert synth.ALR_C * d ** (-2.3 * (d / 350.0) ** 0.28) == pytest.approx(synth.ALR_C * 350.0 ** -2.3, rel=1e-15)
-    row = K[half, half:]
+    assert K.shape == (2 * half + 1, 2 * half + 1)
+    assert K[half, half] == c                      # finite limit at d -> 0
+    one_km = int(round(1.0 / pitch))
+    for a, b in ((0, one_km), (one_km, 0), (0, -one_km), (-one_km, 0)):
+        assert K[half + a, half + b] == pytest.approx(c, rel=1e-15)   # d = 1 km: d^-alpha = 1
+    k350 = c * g["d0_km"] ** -g["a0"]                                 # alpha(d0) = a0
+    for a, b in ((0, half), (half, 0), (0, -half), (-half, 0)):
+        assert K[half + a, half + b] == pytest.approx(k350, rel=1e-13)
+    # alpha(d) < a0 below d0, so K(d) > c d^-a0 there, and the reverse above
+    d = pitch * np.arange(3, half)
+    row = K[half, half + 3:2 * half]
+    assert np.all(row > c * d ** -g["a0"])
     # decreasing beyond 1 km (below it ln d < 0 and the kernel rises from c)
-    assert np.all(np.diff(row[2:]) < 0) and row[1] > row[0]
-    j = 10
-    dj = j * pitch
-    assert row[j] == pytest.approx(synth.ALR_C * dj ** (-2.3 * (dj / 350.0) ** 0.28), rel=1e-13)
+    full_row = K[half, half:]
+    assert np.all(np.diff(full_row[2:]) < 0) and full_row[1] > full_row[0]
+    # symmetric in both axes (radial)
+    np.testing.assert_array_equal(K, K[::-1, :])
+    np.testing.assert_array_equal(K, K.T)
+    # the disk cut at the validity range of Eqs. 12-13
+    Kc = synth.psf_alr(half, pitch)
+    r = pitch * np.hypot(*np.meshgrid(np.arange(-half, half + 1), np.arange(-half, half + 1), indexing="ij"))
+    assert np.all(Kc[r > g["valid_to_km"]] == 0.0)
+    np.testing.assert_array_equal(Kc[r <= g["valid_to_km"]], K[r <= g["valid_to_km"]])
+
+
+def _bands_brute_force(L, edges, kernels):
+    """Pure-Python sums: output pixel (i, j) takes the kernel of the band that
+    holds output row i and sums it over the whole map (Eq. 7, zero outside)."""
+    ny, nx = L.shape
+    S = np.zeros((ny, nx))
+    for i in range(ny):
+        t = next(t for t in range(len(kernels)) if edges[t] <= i < edges[t + 1])
+        K = kernels[t]
+        ky, kx = K.shape
+        cy, cx = (ky - 1) // 2, (kx - 1) // 2
+        for j in range(nx):
+            s = 0.0
+            for a in range(ky):
+                for b in range(kx):
+                    r, q = i + cy - a, j + cx - b
+                    if 0 <= r < ny and 0 <= q < nx:
+                        s += K[a, b] * float(L[r, q])
+            S[i, j] = s
+    return S
+
+
+@pytest.mark.parametrize("edges,shapes", [
+    ((0, 3, 7, 12), ((3, 5), (5, 3), (7, 7))),
+    ((0, 1, 5, 5, 12), ((3, 3), (4, 6), (5, 5), (1, 9))),   # an empty band, an even kernel
+    ((0, 12), ((5, 7),)),
+])
+def test_latitude_band_dispatch_brute_force(edges, shapes):
+    """Sec. 4: each output row uses its own band's kernel over the whole map,
+    so rows next to a band edge draw on the neighbouring band's pixels."""
+    rng = np.random.default_rng(len(edges))
+    L = rng.random((12, 9)).astype(np.float32)
+    # kernels of very different magnitude, so a row given its neighbour's kernel fails
+    kernels = [rng.random(s) * 10.0 ** t for t, s in enumerate(shapes)]
+    want = _bands_brute_force(L, edges, kernels)
+    idx = rng.permutation(L.size)
+    got = latlon.conv_latitude_bands_pixels(L, list(edges), kernels, idx)
+    np.testing.assert_allclose(got, want.ravel()[idx], rtol=1e-13, atol=0)
+    # a single band is the plain "same" convolution
+    if len(shapes) == 1:
+        import oracle
+        np.testing.assert_allclose(got, oracle.conv_same(L, kernels[0]).ravel()[idx], rtol=1e-13)

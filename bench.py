@@ -2,13 +2,20 @@
 
 One step = one lp_convolve of the whole map (rows forward transform, column
 transform x kernel spectrum x inverse, rows inverse transform with crop) with
-the map already resident in HBM.  Default workload: 4096x4096 FP32 city-cluster
-radiance map, 1201x1201 kernel d^-2.5 exp(-d/80 km) cut at 300 km (0.5 km
-pitch), padded to 5400x5400.
+the map already resident in HBM.  Default workload: the continental map,
+16384x16384 FP32 city-cluster radiance (6000 blobs, 20% background), 2001x2001
+kernel d^-2.5 exp(-d/80 km) cut at 500 km (0.5 km pitch), padded to
+18432x18432, run three times on the same map: plain FP32 transforms (`value`,
+`ms_per_step`) and the two split-precision matrix-core forms (BF16 x3 and
+FP16 hi+lo operands, FP32 accumulation) beside it.
 
-Prints one JSON line with the throughput, a roofline entry for the dominant
-kernel (the column stage, timed with HIP events on the stream it runs on) and
-the FP64 CPU oracle timed on a bounded pixel sample on the host cores.
+Each form: W warm-up steps, then exactly K steps between two HIP events with
+nothing else recorded inside (`ms_per_step`); then, separately, K steps with
+an event pair each (`median_ms`) and K steps with per-stage events (the stage
+times and the roofline entry of the dominant kernel, the column stage).  The
+FP64 CPU oracle is timed on a bounded pixel sample on the host cores (all
+threads, and one), and its values on that sample are compared with every
+form's output.
 """
 import argparse
 import hashlib
@@ -30,15 +37,6 @@ PMC_FILES = {"country": os.path.join(ROOT, "profiles", "pmc_cols_conv_country409
              "continental": os.path.join(ROOT, "profiles", "pmc_cols_conv_continental16384.txt")}
 KERNEL_SOURCES = ["paper_1907_02891_amd/csrc/lp_kernels.hip", "paper_1907_02891_amd/csrc/fft_lds.h",
                   "paper_1907_02891_amd/csrc/fft_reg.h", "paper_1907_02891_amd/csrc/lp_internal.h"]
-
-
-def stage_every(steps):
-    """Interval between timed steps that carry the per-stage HIP events.  The
-    four events of a recorded call add about 11 us to it (7% of the 4096^2
-    step), so recording them on every timed step would inflate the step
-    time; about 8 sampled steps inside the timed region give the stage
-    averages."""
-    return max(1, steps // 8)
 
 
 def kernel_source_hash():
@@ -113,13 +111,34 @@ def read_pmc(src_hash, workload, config_name, col_variant):
     return (f + w) * 1024.0, (float(valu) if valu else None)
 
 
-def cpu_leg(oracle_at, n_total, gpu_at, budget_s, unit, what):
+def host_cpu():
+    """The host's core count and CPU model (lscpu), for the CPU baseline."""
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["affinity"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info["lscpu " + k.strip()] = v.strip()
+    except (OSError, ValueError):
+        pass
+    return info
+
+
+def cpu_leg(oracle_at, n_total, gpu_at, budget_s, unit, what, one_core_s=None):
     """The CPU baseline: the FP64 oracle as it stands, timed on the host cores
     on a uniformly drawn sample of output units sized to about budget_s of
     work; its values on that sample are also compared with the GPU result at
     the same units (relative L2 and max error over max |value|).
     oracle_at(idx) -> FP64 values at flat unit indices; gpu_at(idx) -> the
-    GPU's values there."""
+    GPU's values there, or a dict of such functions (one per arithmetic form,
+    all checked on the same sample).  one_core_s: also time the oracle on one
+    thread over a sample sized to about that many seconds."""
     import oracle
     rng = np.random.default_rng(99)
     n = 16
@@ -130,24 +149,46 @@ def cpu_leg(oracle_at, n_total, gpu_at, budget_s, unit, what):
         n = int(max(16, min(n_total, n * min(budget_s, 2.0) / max(dt, 1e-6))))
     n = int(max(16, min(n_total, n * budget_s / 2.0)))
     idx = np.sort(rng.choice(n_total, n, replace=False))
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
     ref = oracle_at(idx)
     dt = time.perf_counter() - t0
-    got = gpu_at(idx)
-    return {"value": n / dt, "unit": unit, "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} uniformly drawn {what}, {dt:.1f} s",
-            "parity": {"units": int(n), "rel_l2": oracle.rel_l2(got, ref),
-                       "max_err_frac": oracle.max_err_frac(got, ref)}}
+    rate = n / dt
+
+    def parity(fn):
+        got = fn(idx)
+        return {"units": int(n), "rel_l2": oracle.rel_l2(got, ref), "max_err_frac": oracle.max_err_frac(got, ref)}
+
+    out = {"value": rate, "unit": unit, "cores": threads, "kind": "oracle",
+           "sample": f"{n} uniformly drawn {what}, {dt:.1f} s on {threads} threads"}
+    if isinstance(gpu_at, dict):
+        out["parity"] = {k: parity(f) for k, f in gpu_at.items()}
+    else:
+        out["parity"] = parity(gpu_at)
+    if one_core_s:
+        n1 = int(max(4, min(n, rate / threads * one_core_s)))
+        idx1 = idx[:n1]
+        oracle.set_num_threads(1)
+        try:
+            t0 = time.perf_counter()
+            oracle_at(idx1)
+            dt1 = time.perf_counter() - t0
+        finally:
+            oracle.set_num_threads(threads)
+        out["one_core"] = {"value": n1 / dt1, "unit": unit, "cores": 1,
+                           "sample": f"the first {n1} units of the same sample, {dt1:.1f} s"}
+    out["host"] = host_cpu()
+    return out
 
 
-def cpu_baseline(R, K, budget_s, y):
+def cpu_baseline(R, K, budget_s, gpu_at, one_core_s=None):
     """The oracle's direct FP64 sum of the same map on sampled output pixels."""
     import oracle
     Rd = R.astype(np.float64)
-    yh = y.cpu().numpy().ravel()
-    return cpu_leg(lambda idx: oracle.conv_same_pixels(Rd, K, idx), R.size, lambda idx: yh[idx],
+    return cpu_leg(lambda idx: oracle.conv_same_pixels(Rd, K, idx), R.size, gpu_at,
                    budget_s, "output pixels/s",
-                   f"output pixels of the same map, FP64 direct sum over the {K.shape[0]}x{K.shape[1]} kernel")
+                   f"output pixels of the same map, FP64 direct sum over the {K.shape[0]}x{K.shape[1]} kernel",
+                   one_core_s)
 
 
 PRECISIONS = {"fp32": (0, "f32", "FP32 FFT convolution"),
@@ -155,24 +196,128 @@ PRECISIONS = {"fp32": (0, "f32", "FP32 FFT convolution"),
                          "FFT convolution, radix-16 passes on MFMA with FP16 hi+lo operands"),
               "bf16x3": (2, "bf16x3 split, f32 accumulate",
                          "FFT convolution, radix-16 passes on MFMA with BF16 x3 operands")}
+# the headline metric: the plain FP32 form beside the split-BF16 matrix-core form
+METRIC = "output pixels/s per MI355X (FP32 vs split-BF16 MFMA FFT) at rel-L2 <=1e-5"
+
+
+def timed_steps(fn, stream, steps):
+    """Wall time of exactly `steps` calls on `stream` between two HIP events,
+    synchronised on both sides; nothing else is recorded inside."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def per_step_ms(fn, stream, steps):
+    """Each of `steps` calls between its own pair of events (a separate pass
+    after the timed one): the per-step times, for the median."""
+    import torch
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    evs[0].record(stream)
+    for k in range(steps):
+        fn()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+
+
+def bench_form(lp, torch, wl, K, x, args, precision, pad, stream, dev):
+    """One arithmetic form on one plan: set-up (plan, spectrum, autotuner),
+    warm-up, the timed steps, then the per-step and per-stage passes.
+    Returns the plan's figures and its output."""
+    ny, nx = x.shape
+    mode, dtype, what = PRECISIONS[precision]
+    t0 = time.perf_counter()
+    plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=pad)
+    plan.set_precision(mode)
+    if args.kernels == "generic":
+        plan.set_kernels(lp.KERNELS_GENERIC)
+    plan.bind(device=dev, stream=stream)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan.set_kernel(K)
+    t_spec = time.perf_counter() - t0
+    y = torch.empty_like(x)
+    t0 = time.perf_counter()
+    tuning = None
+    if args.variants:
+        for st, k in zip((lp.STAGE_ROWS, lp.STAGE_COLUMNS, lp.STAGE_ROWS_INVERSE), args.variants.split(",")):
+            if plan.variant_count(st) > 0:
+                plan.set_variant(st, int(k))
+    elif not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
+        from paper_1907_02891_amd import tune
+        tuning = tune.autotune(plan, x, y, use_cache=False)
+    t_tune = time.perf_counter() - t0
+
+    def step():
+        plan.convolve(x, out=y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ms_total = timed_steps(step, stream, args.steps)
+    wall = time.perf_counter() - w0
+    ms_step = ms_total / args.steps
+    steps_ms = per_step_ms(step, stream, max(args.steps, 20))
+    # per-stage HIP events on every call of a separate pass
+    plan.timing(True, every=1)
+    timed_steps(step, stream, max(args.steps, 20))
+    stage_ms, calls = plan.stage_ms()
+    plan.timing(False)
+    stage_avg = [v / max(calls, 1) for v in stage_ms]
+
+    variants = {}
+    if plan.kernels == lp.KERNELS_SPECIALISED:
+        for name, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS), ("rows_inverse", lp.STAGE_ROWS_INVERSE)):
+            if plan.variant_count(st) > 0:
+                t = (tuning or {}).get("rows" if st != lp.STAGE_COLUMNS else "columns", {})
+                tried = {lp.STAGE_ROWS: t.get("forward_ms", t.get("all", [])), lp.STAGE_COLUMNS: t.get("all", []),
+                         lp.STAGE_ROWS_INVERSE: t.get("inverse_ms", [])}[st]
+                variants[name] = {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
+                                  "tried_ms": [round(v, 5) for v in tried]}
+    py, px = plan.padding
+    res = {"precision": precision, "dtype": dtype, "what": what,
+           "value": ny * nx / (ms_step * 1e-3), "ms_per_step": round(ms_step, 5),
+           "median_ms": round(float(np.median(steps_ms)), 5),
+           "stage_ms": [round(v, 5) for v in stage_avg], "stage_calls": calls,
+           "padding": [py, px], "form": plan.form, "shape": plan.shape,
+           "kernels": "specialised" if plan.kernels == lp.KERNELS_SPECIALISED else "generic",
+           "four_step": plan.column_split[0] > 1, "column_split": plan.column_split,
+           "col_variant": plan.variant(lp.STAGE_COLUMNS) if plan.kernels == lp.KERNELS_SPECIALISED and
+           plan.variant_count(lp.STAGE_COLUMNS) > 0 else None,
+           "variants": variants, "wall_s": round(wall, 4),
+           "setup_s": {"plan_bind": round(t_plan, 3), "kernel_spectrum": round(t_spec, 3),
+                       "autotune": round(t_tune, 3)}}
+    del plan
+    return res, y
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="country",
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="continental",
                     choices=["country", "small", "adjoint", "continental", "large", "slab", "batched", "classes", "reproject",
                              "bands"])
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work (all threads)")
+    ap.add_argument("--cpu-one-core", type=float, default=4.0, help="seconds of oracle work on one thread")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (variant 0 of each stage)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for PMC byte calibration)")
-    ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS),
-                    help="transform arithmetic: FP32 vector ALU, or radix-16 passes on the "
-                         "matrix cores with FP16 hi+lo / BF16 x3 split operands")
+    ap.add_argument("--precision", default="all", choices=list(PRECISIONS) + ["all"],
+                    help="transform arithmetic: FP32 vector ALU, radix-16 passes on the matrix cores with "
+                         "FP16 hi+lo / BF16 x3 split operands, or all three on the same map (FP32 is `value`)")
     ap.add_argument("--kernels", default="auto", choices=["auto", "generic"],
                     help="generic: LDS-staged kernels only (no specialised register kernels)")
     ap.add_argument("--padding", default="config", choices=["config", "window"],
@@ -211,119 +356,86 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-
-    t0 = time.perf_counter()
     pad = (wl.py, wl.px) if args.padding == "config" else lp.window_padding(ny, nx, *K.shape)
     if args.pad:
         pad = tuple(int(v) for v in args.pad.split(","))
-    plan = lp.Plan(ny, nx, *K.shape, pitch_km=wl.pitch_km, padding=pad)
-    mode, dtype, what = PRECISIONS[args.precision]
-    plan.set_precision(mode)
-    if args.kernels == "generic":
-        plan.set_kernels(lp.KERNELS_GENERIC)
-    plan.bind(device=dev, stream=stream)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    plan.set_kernel(K)
-    t_spec = time.perf_counter() - t0
+    forms = ["fp32", "bf16x3", "fp16x2"] if args.precision == "all" else [args.precision]
 
     x = torch.from_numpy(R).to(dev)
-    y = torch.empty_like(x)
-    t0 = time.perf_counter()
-    tuning = None
-    if args.variants:
-        for st, k in zip((lp.STAGE_ROWS, lp.STAGE_COLUMNS, lp.STAGE_ROWS_INVERSE), args.variants.split(",")):
-            if plan.variant_count(st) > 0:
-                plan.set_variant(st, int(k))
-    elif not args.no_tune and plan.kernels == lp.KERNELS_SPECIALISED:
-        from paper_1907_02891_amd import tune
-        tuning = tune.autotune(plan, x, y, use_cache=False)
-    t_tune = time.perf_counter() - t0
-    for _ in range(args.warmup):
-        plan.convolve(x, out=y)
-    torch.cuda.synchronize()
+    results, samples = {}, {}
+    for prec in forms:
+        res, y = bench_form(lp, torch, wl, K, x, args, prec, pad, stream, dev)
+        results[prec] = res
+        samples[prec] = y.cpu().numpy().ravel()
+        del y
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    head = results[forms[0]]
 
-    plan.timing(True, every=stage_every(args.steps))
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.convolve(x, out=y)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms_total = ev0.elapsed_time(ev1)
-    stage_ms, calls = plan.stage_ms()
-    plan.timing(False)
-    ms_step = ms_total / args.steps
-    stage_avg = [s / max(calls, 1) for s in stage_ms]
-
-    py, px = plan.padding
-    four_step = plan.column_split[0] > 1
-    path_b, cols_b, kh_b = (model_bytes_four_step if four_step else model_bytes)(ny, nx, py, px, plan.form)
+    py, px = head["padding"]
+    path_b, cols_b, kh_b = (model_bytes_four_step if head["four_step"] else model_bytes)(ny, nx, py, px, head["form"])
     src_hash = kernel_source_hash()
-    col_variant = plan.variant(lp.STAGE_COLUMNS) if plan.kernels == lp.KERNELS_SPECIALISED and \
-        plan.variant_count(lp.STAGE_COLUMNS) > 0 else None
     config_name = wl.name if args.padding == "config" and not args.pad else f"{wl.name}-p{pad[0]}x{pad[1]}"
-    traffic, valu = read_pmc(src_hash, args.workload, config_name, col_variant)
-    if args.precision != "fp32":
+    traffic, valu = read_pmc(src_hash, args.workload, config_name, head["col_variant"])
+    if forms[0] != "fp32":
         traffic, valu = None, None
-    cols_s = stage_avg[1] * 1e-3
+    cols_s = head["stage_ms"][1] * 1e-3
     achieved = cols_b / cols_s / 1e9
-    col_kernel = "k_cols_reg" if plan.kernels == lp.KERNELS_SPECIALISED else "k_cols_conv"
-    if four_step:
-        col_kernel = "k_long_fwd + k_long_mid + k_long_inv (four-step, P1 x P2 = %d x %d)" % plan.column_split
+    col_kernel = "k_cols_reg" if head["kernels"] == "specialised" else "k_cols_conv"
+    if head["four_step"]:
+        col_kernel = "k_long_fwd + k_long_mid + k_long_inv (four-step, P1 x P2 = %d x %d)" % head["column_split"]
         traffic, valu = None, None
     roofline = {"bound": "hbm", "kernel": col_kernel, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)}
+                "traffic": traffic, "algorithmic_bytes": cols_b, "avg_ms": round(head["stage_ms"][1], 5),
+                "avg_ms_source": "HIP events around the column stage on every call of a pass of "
+                                 f"{head['stage_calls']} steps after the timed ones, on the plan's stream"}
     if valu is not None:
-        # the unit that binds this kernel: VALU issue (no packed FP32): a wave64
-        # instruction takes its SIMD 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
+        # VALU issue (no packed FP32): a wave64 instruction takes its SIMD 4
+        # cycles; 256 CUs x 4 SIMDs at 2.4 GHz
         issue_peak = 256 * 4 * 2.4e9 / 4.0  # wave-instructions per second
         rate = valu / cols_s
         roofline["valu_issue"] = {"wave_instructions": valu, "achieved_per_s": rate,
                                   "peak_per_s": issue_peak, "frac": round(rate / issue_peak, 4)}
 
-    variants = {}
-    if plan.kernels == lp.KERNELS_SPECIALISED:
-        for name, st in (("rows", lp.STAGE_ROWS), ("columns", lp.STAGE_COLUMNS), ("rows_inverse", lp.STAGE_ROWS_INVERSE)):
-            if plan.variant_count(st) > 0:
-                t = (tuning or {}).get("rows" if st != lp.STAGE_COLUMNS else "columns", {})
-                tried = {lp.STAGE_ROWS: t.get("forward_ms", t.get("all", [])), lp.STAGE_COLUMNS: t.get("all", []),
-                         lp.STAGE_ROWS_INVERSE: t.get("inverse_ms", [])}[st]
-                variants[name] = {"chosen": plan.variant(st), "info": plan.variant_info(st, plan.variant(st)),
-                                  "tried_ms": [round(x, 5) for x in tried]}
+    def form_entry(r):
+        return {"value": r["value"], "unit": "output pixels/s", "ms_per_step": r["ms_per_step"],
+                "median_ms": r["median_ms"], "dtype": r["dtype"], "kernels": r["kernels"],
+                "stage_ms": r["stage_ms"],
+                "model_frac": round(path_b / (r["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "setup_s": r["setup_s"], "variants": r["variants"]}
+
+    metric = METRIC if args.precision == "all" else f"output pixels/s per MI355X ({head['what']}) at rel-L2 <=1e-5"
     out = {
-        "metric": f"output pixels/s per MI355X ({what}) at rel-L2 <= 1e-5",
-        "value": ny * nx / (ms_step * 1e-3),
+        "metric": metric,
+        "value": head["value"],
         "unit": "output pixels/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": dtype, "data": "synthetic",
+        "dtype": head["dtype"], "data": "synthetic",
         "config": {"workload": config_name,
                    "ny": ny, "nx": nx, "ky": K.shape[0], "kx": K.shape[1],
                    "padding": [py, px], "pitch_km": wl.pitch_km,
-                   "spectrum_form": {1: "real-quadrant", 2: "complex"}[plan.form],
-                   "cols_per_group": plan.shape[0], "rows_per_group": plan.shape[1],
-                   "precision": args.precision,
-                   "kernels": "specialised" if plan.kernels == lp.KERNELS_SPECIALISED else "generic"},
+                   "spectrum_form": {1: "real-quadrant", 2: "complex"}[head["form"]],
+                   "cols_per_group": head["shape"][0], "rows_per_group": head["shape"][1],
+                   "precision": forms[0], "kernels": head["kernels"]},
         "roofline": roofline,
-        "path": {"stage_ms": [round(s, 5) for s in stage_avg],
+        "median_ms": head["median_ms"],
+        "path": {"stage_ms": head["stage_ms"],
                  "stage_names": ["rows forward", "columns", "rows inverse"],
-                 "stage_sampled_steps": calls,
+                 "stage_calls": head["stage_calls"],
                  "model_bytes": path_b,
-                 "model_GBs": round(path_b / (ms_step * 1e-3) / 1e9, 1),
-                 "model_frac": round(path_b / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                 "wall_s": round(wall, 4)},
-        "setup_s": {"inputs": round(t_gen, 2), "plan_bind": round(t_plan, 3),
-                    "kernel_spectrum": round(t_spec, 3), "autotune": round(t_tune, 3)},
-        "variants": variants,
+                 "model_GBs": round(path_b / (head["ms_per_step"] * 1e-3) / 1e9, 1),
+                 "model_frac": round(path_b / (head["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "wall_s": head["wall_s"]},
+        "setup_s": dict(inputs=round(t_gen, 2), **head["setup_s"]),
+        "variants": head["variants"],
         "kernel_source": src_hash,
     }
+    for prec in forms[1:]:
+        out["split_" + prec] = form_entry(results[prec])
+        out["split_" + prec]["vs_fp32"] = round(results[prec]["value"] / head["value"], 4)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -333,7 +445,9 @@ def main():
         out["copy_calibration_bytes"] = 2 * a.numel() * 4
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(R, K, args.cpu_budget, y)
+        gpu_at = {p: (lambda idx, h=samples[p]: h[idx]) for p in forms}
+        out["cpu_baseline"] = cpu_baseline(R, K, args.cpu_budget, gpu_at if len(forms) > 1 else gpu_at[forms[0]],
+                                           args.cpu_one_core)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     out["paper_context"] = {"px_per_s": 3.28e6, "hardware": "Matlab R2011a, Intel Core i7 2.40 GHz",
                             "workload": "11920x11804 map, ZSB kernel, incl. file output"}
@@ -476,8 +590,10 @@ def bench_classes(args):
         return e0.elapsed_time(e1) / args.steps
 
     ms_sep = timed(run_separate)
-    plan.timing(True, every=stage_every(args.steps))
     ms_step = timed(run_sum)
+    # per-stage events on every call of a separate pass
+    plan.timing(True, every=1)
+    timed_steps(run_sum, stream, max(args.steps, 20))
     stage_ms, calls = plan.stage_ms()
     plan.timing(False)
     stage_avg = [s / max(calls, 1) for s in stage_ms]
@@ -500,7 +616,7 @@ def bench_classes(args):
                      "traffic": None, "algorithmic_bytes": cols_b, "avg_ms": round(stage_avg[1], 5)},
         "path": {"stage_ms": [round(s, 5) for s in stage_avg],
                  "stage_names": ["rows forward (all classes)", "columns (class sum)", "rows inverse"],
-                 "stage_sampled_steps": calls,
+                 "stage_calls": calls,
                  "model_bytes": path_b,
                  "model_frac": round(path_b / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "separate_convolutions_ms": round(ms_sep, 5),

@@ -1,6 +1,13 @@
 """Build the HIP library liblp.so in-tree for gfx950 (hipcc cross-compiles
-without a GPU).  Run as `python -m paper_1907_02891_amd.build`."""
+without a GPU).  Run as `python -m paper_1907_02891_amd.build`.
+
+`python -m paper_1907_02891_amd.build --sanitize` builds a second copy,
+_build/sanitize/liblp.so, whose host code (argument checks, plan logic,
+workspace layout, twiddle tables) carries AddressSanitizer and
+UndefinedBehaviorSanitizer; the GPU code is built as usual.  It is for the
+CPU test suite (LP_LIB_PATH points the binding at it); see README.md."""
 import os
+import shlex
 import subprocess
 import sys
 
@@ -15,15 +22,29 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Wall", "-Wno-unused-function"]
 
 
-def build(verbose=False) -> str:
+# host-side sanitizers only (each flag applies to the host compilation)
+SANITIZE_FLAGS = shlex.split("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+                             "-Xarch_host -fno-sanitize-recover=all -Xarch_host -fno-omit-frame-pointer -g")
+SANITIZE_LIB = os.path.join(ROOT, "_build", "sanitize", "liblp.so")
+
+
+def build(verbose=False, sanitize=False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(_HERE, "csrc")]
+    lib = LIB
+    extra = []
+    odir = os.path.join(_HERE, "csrc")
+    if sanitize:
+        lib = SANITIZE_LIB
+        odir = os.path.dirname(lib)
+        os.makedirs(odir, exist_ok=True)
+        extra = SANITIZE_FLAGS
     objs, procs = [], []
     for src in SOURCES:  # compiled in parallel
         path = os.path.join(_HERE, src)
-        obj = os.path.join(_HERE, "csrc", os.path.basename(src) + ".o")
+        obj = os.path.join(odir, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc, *HIP_FLAGS, *inc, *lang, "-c", path, "-o", obj]
+        cmd = [hipcc, *HIP_FLAGS, *extra, *inc, *lang, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd))
         procs.append((cmd, subprocess.Popen(cmd)))
@@ -31,16 +52,17 @@ def build(verbose=False) -> str:
     for cmd, proc in procs:
         if proc.wait() != 0:
             raise subprocess.CalledProcessError(proc.returncode, cmd)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = lib + ".tmp"
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *extra, "-shared-libsan", "-o", tmp, *objs] \
+        if sanitize else [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -16,7 +16,9 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblp.so")
+# LP_LIB_PATH: another build of the same library (the host-sanitizer build of
+# the CPU test suite); the default is the in-tree liblp.so
+LIB_PATH = os.environ.get("LP_LIB_PATH") or os.path.join(_HERE, "liblp.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1907_02891_amd.build`")

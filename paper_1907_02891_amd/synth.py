@@ -26,13 +26,14 @@ MEAN_CELL_DISTANCE = (math.sqrt(2.0) + math.asinh(1.0)) / 6.0
 
 def radiance_map(ny, nx, n_blobs, bg_frac, sigma_px, rng, *,
                  bg_mu=-4.0, bg_sigma=1.0, peak_mu=3.0, peak_sigma=1.0,
-                 truncate=5.0):
+                 truncate=5.0, centres=None):
     """City-cluster radiance grid, FP32 ny x nx.
 
     Draw order: background mask (Bernoulli(bg_frac) per pixel), background
     values lognormal(bg_mu, bg_sigma), then blob centres (uniform over the
     grid), widths (uniform in sigma_px), peaks lognormal(peak_mu, peak_sigma).
-    Each blob is a Gaussian truncated at `truncate` sigma.
+    Each blob is a Gaussian truncated at `truncate` sigma.  If `centres` is a
+    list, the blob centres (row, column arrays, in pixels) are appended to it.
     """
     R = np.zeros((ny, nx), np.float64)
     if bg_frac > 0:
@@ -43,6 +44,8 @@ def radiance_map(ny, nx, n_blobs, bg_frac, sigma_px, rng, *,
     cx = rng.uniform(0.0, nx, n_blobs)
     sig = rng.uniform(sigma_px[0], sigma_px[1], n_blobs)
     peak = rng.lognormal(peak_mu, peak_sigma, n_blobs)
+    if centres is not None:
+        centres.append((cy.copy(), cx.copy()))
     for y0, x0, s, pk in zip(cy, cx, sig, peak):
         h = int(math.ceil(truncate * s))
         i0, i1 = max(0, int(y0) - h), min(ny, int(y0) + h + 1)
@@ -166,11 +169,12 @@ def country_inputs(seed=COUNTRY.seed, n=4096):
     return R, K
 
 
-def continental_inputs(seed=CONTINENTAL.seed, n=16384):
+def continental_inputs(seed=CONTINENTAL.seed, n=16384, centres=None):
     """16384x16384 map, 20% background, 6000 blobs (sigma 2-40 px); 2001x2001
-    kernel d^-2.5 exp(-d/80 km) cut to a 500 km disk."""
+    kernel d^-2.5 exp(-d/80 km) cut to a 500 km disk.  `centres`: as in
+    radiance_map."""
     rng = np.random.default_rng(seed)
-    R = radiance_map(n, n, 6000, 0.20, (2.0, 40.0), rng)
+    R = radiance_map(n, n, 6000, 0.20, (2.0, 40.0), rng, centres=centres)
     K = psf_powexp(1000, 2.5, 80.0, 0.5, radius_km=500.0)
     return R, K
 
@@ -254,3 +258,26 @@ def sample_pixels(R, n, rng, *, n_bright=None, K=None):
     dim_pool = np.flatnonzero(flat <= np.quantile(flat, 0.5))
     dim = rng.choice(dim_pool, min(n_bright, dim_pool.size), replace=False)
     return np.unique(np.concatenate([uni, top, dim]).astype(np.int64))
+
+
+def sample_pixels_c12(R, centres, rng, n_uniform=2048, n_bright=1024, n_far=1024, min_dist=200.0):
+    """Sample of output pixels for the continental map: n_uniform drawn
+    uniformly, the n_bright brightest input pixels, and n_far drawn uniformly
+    among the pixels at least min_dist pixels from every blob centre (the
+    dark countryside, where FP32 transform error is largest relative to the
+    value).  centres: (row, column) arrays of the blob centres.  Flat indices,
+    sorted, without repeats."""
+    from scipy.spatial import cKDTree
+    ny, nx = R.shape
+    uni = rng.choice(ny * nx, n_uniform, replace=False)
+    flat = R.ravel()
+    top = np.argpartition(flat, -n_bright)[-n_bright:]
+    tree = cKDTree(np.stack([centres[0], centres[1]], axis=1))
+    far = []
+    while len(far) < n_far:
+        cand = rng.choice(ny * nx, 8 * n_far, replace=False)
+        pts = np.stack([cand // nx + 0.5, cand % nx + 0.5], axis=1)
+        d, _ = tree.query(pts)
+        far.extend(cand[d >= min_dist].tolist())
+    far = np.asarray(far[:n_far], np.int64)
+    return np.unique(np.concatenate([uni, top, far]).astype(np.int64))

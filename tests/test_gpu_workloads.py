@@ -65,16 +65,71 @@ def test_country_shape_separable_full_field(lp, torch):
     check(y.cpu().numpy(), oracle.conv_same_separable(R, u, v), "country separable full field")
 
 
-def test_continental_workload_sampled(lp, torch):
-    """16384^2 map, 2001^2 kernel, P = 18432: 1024 sampled output pixels."""
-    R, K = synth.continental_inputs()
-    y, plan = run_full(lp, torch, R, K, (18432, 18432))
-    assert plan.kernels == lp.KERNELS_SPECIALISED
-    rng = np.random.default_rng(43)
-    idx = synth.sample_pixels(R, 1024, rng)
-    check(y.cpu().numpy().ravel()[idx], oracle.conv_same_pixels(R, K, idx), "continental sampled")
-    del y, plan
+PRECISIONS = {"fp32": 0, "fp16x2": 1, "bf16x3": 2}
+
+
+@pytest.fixture(scope="module")
+def continental():
+    """The continental map (16384^2, 2001^2 kernel), its blob centres, and the
+    oracle at 4096 sampled pixels: 2048 uniform, the 1024 brightest input
+    pixels, 1024 at least 200 px from every blob centre."""
+    centres = []
+    R, K = synth.continental_inputs(centres=centres)
+    idx = synth.sample_pixels_c12(R, centres[0], np.random.default_rng(43))
+    return R, K, idx, oracle.conv_same_pixels(R, K, idx)
+
+
+def run_precision(lp, torch, R, K, precision):
+    plan = lp.make_plan(K, *R.shape, padding=(18432, 18432), precision=PRECISIONS[precision])
+    x = torch.from_numpy(R).cuda()
+    y = plan.convolve(x)
+    torch.cuda.synchronize()
+    out = y.cpu().numpy()
+    kern = plan.kernels
+    del x, y, plan
     torch.cuda.empty_cache()
+    return out, kern
+
+
+@pytest.mark.parametrize("precision", list(PRECISIONS))
+def test_continental_workload_sampled(lp, torch, continental, precision):
+    """16384^2 map, 2001^2 kernel, P = 18432, FP32 and the two split-precision
+    matrix-core forms: 4096 sampled output pixels (uniform, brightest, and
+    dark countryside far from every city)."""
+    R, K, idx, ref = continental
+    S, kern = run_precision(lp, torch, R, K, precision)
+    if precision == "fp32":
+        assert kern == lp.KERNELS_SPECIALISED
+    got = S.ravel()[idx]
+    check(got, ref, f"continental {precision} sampled ({len(idx)} px)")
+    # the darkest quarter of the sample on its own: transform round-off is
+    # about uniform in absolute terms, so there it is largest relative to
+    # the value; the bar (max error over the map's maximum) still holds
+    sel = np.argsort(ref)[:len(idx) // 4]
+    em = float(np.max(np.abs(got[sel] - ref[sel])) / np.max(np.abs(ref)))
+    e2 = oracle.rel_l2(got[sel], ref[sel])
+    print(f"continental {precision}: darkest {len(sel)} sampled pixels, rel-L2 {e2:.3e}, "
+          f"max err / max|S| {em:.3e}", flush=True)
+    assert em <= TOL
+
+
+@pytest.fixture(scope="module")
+def continental_separable(continental):
+    """K = u v^T at the continental shape: the oracle's separable form gives
+    the full 16384^2 field in FP64 (2 x 16384^2 x 2001 multiply-adds)."""
+    R = continental[0]
+    u, v = synth.psf_separable(2001, 2001, np.random.default_rng(44))
+    return u, v, oracle.conv_same_separable(R, u, v)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", list(PRECISIONS))
+def test_continental_separable_full_field(lp, torch, continental, continental_separable, precision):
+    """Full-field parity at the continental shape, P = 18432, every form."""
+    R = continental[0]
+    u, v, ref = continental_separable
+    S, _ = run_precision(lp, torch, R, np.outer(u, v), precision)
+    check(S, ref, f"continental separable full field {precision}")
 
 
 @pytest.mark.parametrize("case", [(17000, 8, 1001, 3, (18432, 12)), (6, 17000, 3, 1201, (8, 18432))],
@@ -140,10 +195,28 @@ def test_adjoint_workload_autograd_gradient(lp, torch, adjoint_case):
     grad = x.grad.cpu().numpy()
     g = (2.0 * w * r.detach().cpu().numpy()).astype(np.float32)
     check(grad, oracle.adjoint_sparse(sites, g, R0.shape, K), "autograd gradient vs oracle")
-    # the oracle gradient with FP64 residuals, for the record (dim sites carry
-    # large weights 1/m^2, so FP32 forward error enters it)
-    ref64 = oracle.adjoint_sparse(sites, 2.0 * w * (oracle.conv_same_pixels(R0, K, sites) - m), R0.shape, K)
-    print(f"autograd gradient vs FP64-residual oracle gradient: rel-L2 {oracle.rel_l2(grad, ref64):.3e}")
+    # Against the FP64 oracle gradient (FP64 forward, FP64 residuals).  The
+    # gradient is the transposed operator applied to the weighted site
+    # residuals 2 w (S - m); the GPU's residuals differ from the FP64 ones by
+    # its forward error at the sites, S_gpu - S_64, about 1e-7 of max|S| in
+    # absolute terms.  So the gradient differs from the FP64 one by C^T of
+    # 2 w (S_gpu - S_64) -- asserted as a decomposition, to the bar -- and
+    # its relative error tracks rho = |w (S_gpu - S_64)| / |w (S_64 - m)|,
+    # the relative perturbation of the weighted residual vector.  With the
+    # workload's weights 1/m^2 dim sites amplify that absolute error and rho
+    # is about 2e-2 (a property of the loss, not of the kernels); with
+    # uniform weights it is about 2e-6, and the gradient meets the bar.
+    S64 = oracle.conv_same_pixels(R0, K, sites)
+    s_gpu = r.detach().cpu().numpy() + m
+    ref64 = oracle.adjoint_sparse(sites, 2.0 * w * (S64 - m), R0.shape, K)
+    rho = float(np.linalg.norm(w * (s_gpu - S64)) / np.linalg.norm(w * (S64 - m)))
+    e64 = oracle.rel_l2(grad, ref64)
+    dec = oracle.adjoint_sparse(sites, 2.0 * w * (s_gpu - S64), R0.shape, K)
+    e_dec = float(np.linalg.norm((grad - ref64) - dec) / np.linalg.norm(ref64))
+    print(f"autograd gradient vs FP64 oracle gradient, weights 1/m^2: rel-L2 {e64:.3e}; "
+          f"residual perturbation rho {rho:.3e}; after removing C^T 2w(S_gpu - S_64): {e_dec:.3e}", flush=True)
+    assert e_dec <= TOL
+    assert e64 <= 1.5 * rho + TOL
     # Central differences on the 50 pixels with the largest gradient.  The
     # loss is quadratic in R, so central differences are exact up to
     # round-off for any step; what limits them is the FP32 round-off of the
@@ -188,6 +261,12 @@ def test_adjoint_workload_autograd_gradient(lp, torch, adjoint_case):
     ru = Su.reshape(-1)[st].double() - mt
     (torch.from_numpy(wu).cuda() * ru * ru).sum().backward()
     gu = xu.grad.cpu().numpy().ravel()
+    gu64 = oracle.adjoint_sparse(sites, 2.0 * wu * (S64 - m), R0.shape, K).ravel()
+    rho_u = float(np.linalg.norm(ru.detach().cpu().numpy() + m - S64) / np.linalg.norm(S64 - m))
+    eu64 = oracle.rel_l2(gu, gu64)
+    print(f"autograd gradient vs FP64 oracle gradient, uniform weights: rel-L2 {eu64:.3e} (rho {rho_u:.3e})",
+          flush=True)
+    assert eu64 <= TOL
     pix_u = np.argsort(-np.abs(gu))[:50]
     fdu = central(wu, pix_u, 1.0e2)
     e_u = float(np.linalg.norm(fdu - gu[pix_u]) / np.linalg.norm(gu[pix_u]))

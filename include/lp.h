@@ -148,6 +148,28 @@ int lp_plan_read_spectrum(lp_plan *plan, float *out);
  * LP_E_STATE (no spectrum), LP_E_NOMEM (unbound), LP_E_DEVICE. */
 int lp_convolve(lp_plan *plan, const float *radiance, float *out);
 
+/* For callers that cannot allocate device memory at call time (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * lp_convolve with the intermediate spectra of the map held in a scratch
+ * array that is part of the library itself (a device-resident array of
+ * LP_NOALLOC_MAX_BYTES on each GPU the library runs on, kept until the
+ * process ends) instead of in the bound workspace.  Same arguments, same
+ * kernels, same result bits as lp_convolve; the plan must still be bound
+ * (its workspace holds the kernel spectrum and the twiddle tables) and its
+ * workspace must be on the current device.  The call allocates nothing: no
+ * hipMalloc, no allocating library routine.  Every call on one GPU shares
+ * that GPU's array, which keeps the last call's contents (nothing in it
+ * needs to start at zero): calls that overlap on one GPU -- from several
+ * plans, streams or host threads at once -- race and give wrong results;
+ * serialise them.  Errors: LP_E_INVALID (null, or the workspace on another
+ * device), LP_E_STATE (no spectrum, several classes), LP_E_SIZE (the
+ * intermediate, (Px/2+1 rounded up to even) * ny * 8 bytes, exceeds
+ * LP_NOALLOC_MAX_BYTES, or the padded columns take the four-step stage,
+ * whose scratch lives in the workspace), LP_E_NOMEM (unbound),
+ * LP_E_DEVICE. */
+#define LP_NOALLOC_MAX_BYTES (128u << 20)
+int lp_convolve_noalloc(lp_plan *plan, const float *radiance, float *out);
+
 /* Transpose of lp_convolve (correlation with K: the same kernels with the
  * conjugate spectrum), for gradients: grad_in = C^T grad_out.  Device FP32
  * ny*nx in and out (may alias).  Same errors as lp_convolve. */

@@ -15,6 +15,8 @@
 
 #include "lp_internal.h"
 
+static_assert(lp::kNoAllocBytes == LP_NOALLOC_MAX_BYTES, "scratch array size");
+
 namespace {
 
 thread_local std::string g_err;
@@ -488,7 +490,7 @@ bool attributes_set = false;
 // The three stages.  ins: nin maps (nin = the plan's classes for a class
 // sum, else 1); kh_class: the class whose spectrum a single-map call uses.
 int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjoint, int kh_class,
-             const char *who)
+             const char *who, float2 *w_scratch = nullptr)
 {
     if (!p) return fail(LP_E_INVALID, "%s: null plan", who);
     if (!ins || !out) return fail(LP_E_INVALID, "%s: null data pointer", who);
@@ -505,7 +507,9 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     }
     hipEvent_t *ev = rec ? &p->ev[4 * p->ev_calls] : nullptr;
     if (rec && (e = hipEventRecord(ev[0], p->stream)) != hipSuccess) return fail_hip(e, who);
-    float2 *W = reinterpret_cast<float2 *>(p->ws + p->off_w);
+    // the intermediate: the workspace's, or the scratch array given for it
+    char *const wbase = w_scratch ? reinterpret_cast<char *>(w_scratch) : p->ws + p->off_w;
+    float2 *W = reinterpret_cast<float2 *>(wbase);
     const lp::RowArgs ra = row_args(p);
     lp::ColArgs ca = col_args(p);
     ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
@@ -526,7 +530,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         rr.tw_i2 = twr + p->twr_off[3];
     }
     for (int t = 0; t < nin; ++t) {
-        float2 *Wt = reinterpret_cast<float2 *>(p->ws + p->off_w + static_cast<size_t>(t) * p->w_class);
+        float2 *Wt = reinterpret_cast<float2 *>(wbase + static_cast<size_t>(t) * p->w_class);
         e = rspec ? lp::launch_rows_r2c_reg(ins[t], Wt, rr, p->row_spec, p->stream)
                   : lp::launch_rows_r2c(ins[t], Wt, ra, p->t_rows, p->stream);
         if (e != hipSuccess) return fail_hip(e, "rows forward launch");
@@ -953,6 +957,36 @@ int lp_convolve(lp_plan *p, const float *radiance, float *out)
     if (p && p->classes != 1)
         return fail(LP_E_STATE, "lp_convolve on a plan of %d classes: use lp_convolve_classes", p->classes);
     return run_path(p, &radiance, 1, out, false, 0, "lp_convolve");
+}
+
+int lp_convolve_noalloc(lp_plan *p, const float *radiance, float *out)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "lp_convolve_noalloc: null plan");
+    if (!radiance || !out) return fail(LP_E_INVALID, "lp_convolve_noalloc: null data pointer");
+    if (p->classes != 1)
+        return fail(LP_E_STATE, "lp_convolve_noalloc on a plan of %d classes", p->classes);
+    if (p->long_cols)
+        return fail(LP_E_SIZE, "lp_convolve_noalloc: padded columns of %lld take the four-step stage, "
+                    "whose scratch lives in the workspace", (long long)p->py);
+    if (p->w_class > LP_NOALLOC_MAX_BYTES)
+        return fail(LP_E_SIZE, "lp_convolve_noalloc: the intermediate takes %zu bytes, beyond the "
+                    "%zu-byte scratch array", p->w_class, static_cast<size_t>(LP_NOALLOC_MAX_BYTES));
+    if (!p->bound) return fail(LP_E_NOMEM, "lp_convolve_noalloc: no workspace bound");
+    if (p->form == LP_FORM_NONE) return fail(LP_E_STATE, "lp_convolve_noalloc: kernel spectrum not computed");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "lp_convolve_noalloc: current device");
+    hipPointerAttribute_t attr{};
+    if ((e = hipPointerGetAttributes(&attr, p->ws)) != hipSuccess)
+        return fail_hip(e, "lp_convolve_noalloc: workspace attributes");
+    if (attr.device != dev)
+        return fail(LP_E_INVALID, "lp_convolve_noalloc: the plan's workspace is on device %d, device %d is current",
+                    attr.device, dev);
+    void *scratch = nullptr;
+    if ((e = lp::noalloc_scratch(dev, &scratch)) != hipSuccess)
+        return fail_hip(e, "lp_convolve_noalloc: scratch array address");
+    return run_path(p, &radiance, 1, out, false, 0, "lp_convolve_noalloc", static_cast<float2 *>(scratch));
 }
 
 int lp_adjoint(lp_plan *p, const float *grad_out, float *grad_in)

@@ -64,6 +64,12 @@ struct ColArgs {
     int64_t kh_stride;  // bytes from one class's spectrum to the next
 };
 
+// Size of the device-resident scratch array of lp_convolve_noalloc (one map's
+// intermediate spectra), and the lookup of its address on a device (the
+// current one; lp_noalloc.hip).
+constexpr size_t kNoAllocBytes = size_t{128} << 20;
+hipError_t noalloc_scratch(int device, void **ptr);
+
 // Bytes of the fragment table of the split-precision radix-16 passes (both
 // directions, the larger of the two split forms).
 constexpr size_t kFragmentBytes = 2 * 6 * 64 * 16;

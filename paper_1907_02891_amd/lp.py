@@ -33,6 +33,7 @@ PRECISION_FP32, PRECISION_SPLIT_FP16, PRECISION_SPLIT_BF16 = 0, 1, 2
 MAX_CLASSES = 16
 MAX_PY, MAX_PX = 131072, 40958
 MAX_COLUMN_TILE = 20480  # longer padded columns take the four-step column stage
+NOALLOC_MAX_BYTES = 128 << 20  # scratch array of lp_convolve_noalloc
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -73,6 +74,7 @@ _SIGS = {
     "lp_plan_read_spectrum": ([_vp, _fp], ctypes.c_int),
     "lp_convolve": ([_vp, _vp, _vp], ctypes.c_int),
     "lp_adjoint": ([_vp, _vp, _vp], ctypes.c_int),
+    "lp_convolve_noalloc": ([_vp, _vp, _vp], ctypes.c_int),
     "lp_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_stage_ms": ([_vp, _dp, ctypes.c_int, _ip], ctypes.c_int),
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
@@ -295,6 +297,16 @@ class Plan:
         _ordered(self.stream, [radiance, out],
                  lambda: _check(_lib.lp_convolve(self._p, ctypes.c_void_p(radiance.data_ptr()),
                                                  ctypes.c_void_p(out.data_ptr()))))
+        return out
+
+    def convolve_noalloc(self, radiance, out):
+        """lp_convolve_noalloc: as convolve, with the intermediate in the
+        library's own device scratch array (the call allocates nothing; `out`
+        must be given).  Calls that overlap on one GPU race."""
+        out = self._io(radiance, out)
+        _ordered(self.stream, [radiance, out],
+                 lambda: _check(_lib.lp_convolve_noalloc(self._p, ctypes.c_void_p(radiance.data_ptr()),
+                                                         ctypes.c_void_p(out.data_ptr()))))
         return out
 
     def adjoint(self, grad_out, out=None):

@@ -55,6 +55,7 @@ def workloads():
         "adjoint": (synth.ADJOINT, lambda: synth.adjoint_inputs()[:2]),
         "continental": (synth.CONTINENTAL, synth.continental_inputs),
         "large": (synth.LARGE, synth.large_inputs),
+        "paper": (synth.PAPER, synth.paper_inputs),
     }
 
 
@@ -308,7 +309,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="continental",
                     choices=["country", "small", "adjoint", "continental", "large", "slab", "batched", "classes", "reproject",
-                             "bands"])
+                             "bands", "paper"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle work (all threads)")
     ap.add_argument("--cpu-one-core", type=float, default=4.0, help="seconds of oracle work on one thread")
     ap.add_argument("--no-cpu", action="store_true")

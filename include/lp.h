@@ -246,7 +246,9 @@ int lp_plan_kernels(const lp_plan *plan);
  * transforms per workgroup, min waves per SIMD, tiles per workgroup (0: a
  * persistent loop; always 1 for the column stage), length, half exchange
  * (1: the passes exchange real and imaginary parts through LDS separately,
- * halving the buffer so that twice as many workgroups fit on a CU)}.
+ * halving the buffer so that twice as many workgroups fit on a CU), staged
+ * (row stages: 1 if the intermediate moves between HBM and LDS in 16-byte
+ * chunks of two spectrum columns)}.
  * LP_STAGE_ROWS selects the variant of both row stages (and reports the
  * forward one); LP_STAGE_ROWS_INVERSE the inverse row stage alone, so the
  * two directions may run different specialisations of the same length. */

@@ -14,6 +14,66 @@
 
 namespace lp {
 
+// Pointers known to address global memory.  A pointer the compiler cannot
+// trace to a kernel argument (one read from a device table of batch items,
+// or reassigned on some path) is generic, and its loads and stores become
+// flat instructions; those count against both the memory and the LDS wait
+// counters, so every LDS wait of a pass would also wait for the HBM traffic
+// in flight.  Cast to the global address space, they are global loads and
+// stores.
+template <class T>
+using gptr = T __attribute__((address_space(1))) *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p)
+{
+    return (gptr<T>)p;
+}
+// float2 load and store through a global pointer of another element type
+// (the vector type's own copy operations take generic references)
+typedef float lp_f2v __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ float2 gload2(gptr<const T> p)
+{
+    const lp_f2v v = *(gptr<const lp_f2v>)p;
+    return make_float2(v.x, v.y);
+}
+template <class T>
+__device__ __forceinline__ void gstore2(gptr<T> p, float2 x)
+{
+    const lp_f2v v = {x.x, x.y};
+    *(gptr<lp_f2v>)p = v;
+}
+
+// Buffer resources: a base address and a size in bytes held in scalar
+// registers, so that each access needs only a 32-bit per-lane byte offset
+// (no 64-bit address arithmetic per element, fewer vector registers).
+// Accesses past the size read zero and write nothing.
+typedef __amdgpu_buffer_rsrc_t lp_rsrc;
+typedef unsigned lp_u2v __attribute__((__vector_size__(2 * sizeof(unsigned))));  // the builtins' 64-bit type
+__device__ __forceinline__ lp_rsrc buffer_rsrc(const void *base, unsigned bytes)
+{
+    // third descriptor word for raw (unformatted) 32-bit data on gfx9-family parts
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), static_cast<short>(0), static_cast<int>(bytes),
+                                             0x00020000);
+}
+__device__ __forceinline__ float2 bload2(lp_rsrc r, unsigned off)
+{
+    const lp_u2v v = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+    float2 f;
+    __builtin_memcpy(&f, &v, sizeof f);
+    return f;
+}
+__device__ __forceinline__ float bload1(lp_rsrc r, unsigned off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ void bstore2(lp_rsrc r, unsigned off, float2 x)
+{
+    lp_u2v v;
+    __builtin_memcpy(&v, &x, sizeof v);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }

@@ -214,7 +214,7 @@ constexpr int lds_words(int n, int rw) { return rw ? (n / rw) * lds_pitch(rw) : 
 // (tt, g), tt in [0, TF), takes butterflies i = tt + s * TF.  LIN / LOUT are
 // the layouts of the buffer it reads / writes (LOUT must be R when P == 1
 // and 0 otherwise).
-template <int N, int R, int P, int TF, int G, int LIN>
+template <int N, int R, int P, int TF, int G, int LIN, bool JM = false>
 struct RegPass {
     static constexpr int RADIX = R;
     static constexpr int NB = N / R;
@@ -287,9 +287,35 @@ struct RegPass {
             for (int s = 0; s < S; ++s) {
                 const int i = tt + s * TF;
                 if (valid(i)) {
-                    const float2 *t = tw + (i % P) * (R - 1);
+                    // table exp(-2 pi i j k / (P R)), k = i mod P: at (j - 1) P + k
+                    // (JM) or at k (R - 1) + j - 1
+                    constexpr int SJ = JM ? P : 1;
+                    const float2 *t = JM ? tw + (i % P) : tw + (i % P) * (R - 1);
 #pragma unroll
-                    for (int j = 1; j < R; ++j) v[s][j] = INV ? cmulc(v[s][j], t[j - 1]) : cmul(v[s][j], t[j - 1]);
+                    for (int j = 1; j < R; ++j)
+                        v[s][j] = INV ? cmulc(v[s][j], t[(j - 1) * SJ]) : cmul(v[s][j], t[(j - 1) * SJ]);
+                }
+            }
+        }
+    }
+
+    // the same through a buffer resource over the table (32-bit offsets)
+    static constexpr unsigned TABLE_BYTES = static_cast<unsigned>(P) * (R - 1) * 8u;
+    template <bool INV>
+    __device__ __forceinline__ static void twiddle(float2 (&v)[S][R], lp_rsrc tw, int tt)
+    {
+        if constexpr (P > 1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = tt + s * TF;
+                if (valid(i)) {
+                    constexpr unsigned SJ = JM ? P * 8u : 8u;
+                    const unsigned t = JM ? static_cast<unsigned>(i % P) * 8u : static_cast<unsigned>(i % P) * ((R - 1) * 8u);
+#pragma unroll
+                    for (int j = 1; j < R; ++j) {
+                        const float2 w = bload2(tw, t + (j - 1) * SJ);
+                        v[s][j] = INV ? cmulc(v[s][j], w) : cmul(v[s][j], w);
+                    }
                 }
             }
         }

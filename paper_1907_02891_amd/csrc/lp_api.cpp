@@ -150,15 +150,20 @@ void make_fft(int64_t n, lp::FftDesc *d, std::vector<float> *tw, int split)
 }
 
 // Twiddles of one pass of radix r after sub-transforms of length p:
-// exp(-2 pi i j k / (p r)) at k * (r - 1) + (j - 1), appended to *tw.
-void pass_table(int64_t p, int r, std::vector<float> *tw)
+// exp(-2 pi i j k / (p r)), appended to *tw at k * (r - 1) + (j - 1), or with
+// jmaj at (j - 1) * p + k (the specialised kernels give consecutive lanes
+// consecutive k, so that for each j a wave reads one contiguous run).
+void pass_table(int64_t p, int r, bool jmaj, std::vector<float> *tw)
 {
+    const size_t base = tw->size();
+    tw->resize(base + 2 * static_cast<size_t>(p) * (r - 1));
     for (int64_t k = 0; k < p; ++k)
         for (int j = 1; j < r; ++j) {
             double c, s;
             exp_frac(j * k, p * r, &c, &s);
-            tw->push_back(static_cast<float>(c));
-            tw->push_back(static_cast<float>(-s));
+            const size_t at = jmaj ? static_cast<size_t>(j - 1) * p + k : static_cast<size_t>(k) * (r - 1) + (j - 1);
+            (*tw)[base + 2 * at] = static_cast<float>(c);
+            (*tw)[base + 2 * at + 1] = static_cast<float>(-s);
         }
 }
 
@@ -172,13 +177,13 @@ size_t spec_table_len(int r0, int r1, int r2)
            static_cast<size_t>(r2) * (r1 - 1) + static_cast<size_t>(r2) * r1 * (r0 - 1);
 }
 
-void spec_tables(int r0, int r1, int r2, std::vector<float> *tw, size_t off[4])
+void spec_tables(int r0, int r1, int r2, bool jmaj, std::vector<float> *tw, size_t off[4])
 {
     const int tabs[4][2] = {{r0, r1}, {r0 * r1, r2}, {r2, r1}, {r2 * r1, r0}};
     tw->clear();
     for (int t = 0; t < 4; ++t) {
         off[t] = tw->size() / 2;
-        pass_table(tabs[t][0], tabs[t][1], tw);
+        pass_table(tabs[t][0], tabs[t][1], jmaj, tw);
     }
 }
 
@@ -355,11 +360,11 @@ void build_spec_tables(lp_plan *p)
     p->twc.clear();
     if (p->col_spec >= 0) {
         const lp::ColSpec c = lp::kColSpecs[p->col_spec];
-        spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
+        spec_tables(c.r0, c.r1, c.r2, c.jmaj != 0, &p->twc, p->twc_off);
     } else if (p->long_cols && p->mid_spec >= 0) {
         // the four-step middle transforms (length P2)
         const lp::ColSpec c = lp::kColSpecs[p->mid_spec];
-        spec_tables(c.r0, c.r1, c.r2, &p->twc, p->twc_off);
+        spec_tables(c.r0, c.r1, c.r2, c.jmaj != 0, &p->twc, p->twc_off);
     }
     // forward tables from the forward row variant, inverse ones from the
     // inverse variant, concatenated
@@ -370,8 +375,8 @@ void build_spec_tables(lp_plan *p)
         const lp::RowSpec f = lp::kRowSpecs[p->row_spec], i = lp::kRowSpecs[p->row_spec_inv];
         size_t off_f[4], off_i[4];
         std::vector<float> ti;
-        spec_tables(f.r0, f.r1, f.r2, &p->twr, off_f);
-        spec_tables(i.r0, i.r1, i.r2, &ti, off_i);
+        spec_tables(f.r0, f.r1, f.r2, false, &p->twr, off_f);
+        spec_tables(i.r0, i.r1, i.r2, false, &ti, off_i);
         const size_t base = p->twr.size() / 2;
         p->twr.insert(p->twr.end(), ti.begin(), ti.end());
         p->twr_off[0] = off_f[0];
@@ -743,23 +748,23 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
 {
     clear_error();
     if (!p || !info) return fail(LP_E_INVALID, "null argument");
-    int v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
         const int i = lp::row_spec_index(static_cast<int>(p->m), k);
         if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
         const lp::RowSpec c = lp::kRowSpecs[i];
-        const int t[9] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half};
-        std::copy(t, t + 9, v);
+        const int t[10] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half, c.stage};
+        std::copy(t, t + 10, v);
     } else if (stage == LP_STAGE_COLUMNS) {
         const int i = lp::col_spec_index(static_cast<int>(p->py), k);
         if (i < 0) return fail(LP_E_INVALID, "no column variant %d", k);
         const lp::ColSpec c = lp::kColSpecs[i];
-        const int t[9] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half};
-        std::copy(t, t + 9, v);
+        const int t[10] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half, 0};
+        std::copy(t, t + 10, v);
     } else {
         return fail(LP_E_INVALID, "unknown stage %d", stage);
     }
-    for (int i = 0; i < n && i < 9; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 10; ++i) info[i] = v[i];
     return LP_OK;
 }
 
@@ -1188,8 +1193,8 @@ void batch_group_tables(lp_batch::Group &g)
     g.row_spec = lp::row_spec_index(static_cast<int>(g.m), g.row_variant);
     const lp::ColSpec c = lp::kColSpecs[g.col_spec];
     const lp::RowSpec r = lp::kRowSpecs[g.row_spec];
-    spec_tables(c.r0, c.r1, c.r2, &g.twc, g.twc_off);
-    spec_tables(r.r0, r.r1, r.r2, &g.twr, g.twr_off);
+    spec_tables(c.r0, c.r1, c.r2, c.jmaj != 0, &g.twc, g.twc_off);
+    spec_tables(r.r0, r.r1, r.r2, false, &g.twr, g.twr_off);
 }
 
 void batch_destroy_graph(lp_batch *b)

@@ -142,6 +142,12 @@ namespace lp {
 struct ColSpec {
     int n, tf, r0, r1, r2, occ;
     int half = 0;
+    // order of the pass twiddle tables (the same for every variant of a
+    // length): 0: per butterfly, twiddle j of butterfly class k at
+    // k (R - 1) + j - 1 (one load instruction takes several of a thread's
+    // twiddles); 1: per twiddle, at (j - 1) P + k (one load instruction reads
+    // a contiguous run across the lanes).  Chosen by measurement per length.
+    int jmaj = 0;
 };
 constexpr ColSpec kColSpecs[] = {
     {5400, 360, 20, 18, 15, 5},
@@ -150,8 +156,8 @@ constexpr ColSpec kColSpecs[] = {
     {5400, 225, 24, 25, 9, 0},
     {4800, 320, 16, 15, 20, 5},
     {4800, 320, 20, 15, 16, 5},
-    {18432, 768, 32, 24, 24, 6, 1},
-    {18432, 768, 32, 24, 24, 0},
+    {18432, 768, 32, 24, 24, 6, 1, 1},
+    {18432, 768, 32, 24, 24, 0, 0, 1},
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},
     {512, 64, 8, 8, 8, 0},
@@ -166,8 +172,26 @@ constexpr ColSpec kColSpecs[] = {
     {3240, 270, 18, 12, 15, 0},
     {3600, 240, 16, 15, 15, 0},
     {4320, 360, 20, 18, 12, 5},
+    {13500, 450, 30, 30, 15, 4, 1},
+    {13500, 450, 30, 30, 15, 0},
+    {13500, 450, 15, 30, 30, 4, 1},
 };
 constexpr int kNumColSpecs = sizeof kColSpecs / sizeof kColSpecs[0];
+
+// Twiddle-table order of the column specialisations of length n.
+constexpr bool col_jmaj(int n)
+{
+    for (int i = 0; i < kNumColSpecs; ++i)
+        if (kColSpecs[i].n == n) return kColSpecs[i].jmaj != 0;
+    return false;
+}
+constexpr bool col_jmaj_consistent()
+{
+    for (int i = 0; i < kNumColSpecs; ++i)
+        if (col_jmaj(kColSpecs[i].n) != (kColSpecs[i].jmaj != 0)) return false;
+    return true;
+}
+static_assert(col_jmaj_consistent(), "every variant of a column length shares its twiddle order");
 
 struct ColRegArgs {
     int32_t ny;          // stored rows per column
@@ -219,6 +243,12 @@ namespace lp {
 struct RowSpec {
     int m, tf, r0, r1, r2, b, occ, pf;
     int half = 0;  // exchanges in two halves (half the LDS); occ is then exact, pf must be 1
+    // stage: the intermediate goes between HBM and the LDS in 16-byte chunks
+    // (two spectrum columns of one row; the lanes of a pair cover one 32-byte
+    // run of the two-column interleave), so each load or store instruction
+    // touches half the cache lines of per-element accesses; full exchange,
+    // one tile per workgroup
+    int stage = 0;
 };
 constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 2, 4, 1},
@@ -237,12 +267,16 @@ constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 2, 4, 1, 1},
     {2400, 160, 15, 16, 10, 2, 4, 1},
     {2400, 160, 16, 15, 10, 2, 4, 1},
+    {6750, 256, 30, 15, 15, 2, 4, 1, 1},
+    {6750, 256, 30, 15, 15, 2, 0, 1},
+    {6750, 256, 30, 15, 15, 1, 4, 1, 1},
     {13500, 512, 30, 30, 15, 2, 4, 1, 1},
     {13500, 512, 30, 30, 15, 1, 4, 1, 1},
     {9216, 384, 24, 24, 16, 2, 0, 1},
     {9216, 384, 16, 24, 24, 1, 2, 1},
     {9216, 256, 16, 24, 24, 2, 2, 1},
     {9216, 384, 24, 24, 16, 1, 0, 1},
+    {9216, 384, 24, 24, 16, 2, 0, 1, 0, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
     {1440, 120, 15, 12, 8, 2, 0, 1},
     {1440, 128, 12, 12, 10, 2, 3, 0},

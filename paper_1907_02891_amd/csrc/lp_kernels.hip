@@ -451,12 +451,13 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
                                                                          const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
+    constexpr bool JM = col_jmaj(N);
     using F0 = RegPass<N, R0, 1, TF, 1, 0>;
-    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
-    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0, JM>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0, JM>;
     using I0 = RegPass<N, R2, 1, TF, 1, 0>;
-    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
-    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2, JM>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0, JM>;
     const int tt = threadIdx.x;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
@@ -470,11 +471,16 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     // intermediate with C = 2^lc interleaved columns: element i of column v
     // at ((v / C) * ny + i) * C + v % C, the spectrum likewise with ku rows
     const int lc = a.lc, cm = (1 << lc) - 1;
-    float2 *col = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
+    float2 *const colp = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
+    // the column's ny stored values through a buffer resource: element n at
+    // byte 8 (n << lc), 32-bit offsets from a base held in scalar registers
+    const unsigned colb = static_cast<unsigned>((((ny - 1) << lc) + 1) * 8);
+    const lp_rsrc col = buffer_rsrc(colp, colb);
 
     // forward transform of one column and product with one spectrum, left in
     // x2 in the order the inverse's first pass takes it
-    auto forward = [&](const float2 *__restrict__ src, const void *kh, float2 (&x2)[F2::S][R2]) {
+    auto forward = [&](const float2 *srcp, const void *kh, float2 (&x2)[F2::S][R2]) {
+        const lp_rsrc src = buffer_rsrc(srcp, colb);
         float2 x0[F0::S][R0];
         if (act) {
 #pragma unroll
@@ -484,7 +490,8 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                     for (int j = 0; j < R0; ++j) {
                         const int n = i + j * F0::NB;
-                        x0[s][j] = (n < ny) ? src[n << lc] : make_float2(0.f, 0.f);
+                        if (n < ny) x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
+                        else x0[s][j] = make_float2(0.f, 0.f);
                     }
                 }
             }
@@ -495,7 +502,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
         float2 x1[F1::S][R1];
         if (act) {
             F1::load(x1, lds, tt, 0);
-            F1::template twiddle<false>(x1, a.tw_f1, tt);
+            F1::template twiddle<false>(x1, buffer_rsrc(a.tw_f1, F1::TABLE_BYTES), tt);
             F1::template butterfly<false>(x1, tt);
         }
         __syncthreads();
@@ -503,7 +510,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
         __syncthreads();
         if (act) {
             F2::load(x2, lds, tt, 0);
-            F2::template twiddle<false>(x2, a.tw_f2, tt);
+            F2::template twiddle<false>(x2, buffer_rsrc(a.tw_f2, F2::TABLE_BYTES), tt);
             F2::template butterfly<false>(x2, tt);
             // Eq. 9: pixel-wise product with the kernel spectrum, element u = i + j NB
 #pragma unroll
@@ -511,19 +518,21 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
                 const int i = tt + s * TF;
                 if (F2::NB % TF == 0 || i < F2::NB) {
                     if constexpr (FORM == 1) {
-                        const float *kq = static_cast<const float *>(kh) +
+                        const float *kqp = static_cast<const float *>(kh) +
                                           ((static_cast<int64_t>(v >> lc) * a.ku) << lc) + (v & cm);
+                        const lp_rsrc kq = buffer_rsrc(kqp, static_cast<unsigned>((((a.ku - 1) << lc) + 1) * 4));
 #pragma unroll
                         for (int j = 0; j < R2; ++j) {
                             const int u = i + j * F2::NB;
-                            x2[s][j] = cscale(x2[s][j], kq[((2 * u <= N) ? u : N - u) << lc]);
+                            x2[s][j] = cscale(x2[s][j], bload1(kq, static_cast<unsigned>(((2 * u <= N) ? u : N - u) << lc) * 4u));
                         }
                     } else {
-                        const float2 *kc = static_cast<const float2 *>(kh) +
+                        const float2 *kcp = static_cast<const float2 *>(kh) +
                                            ((static_cast<int64_t>(v >> lc) * N) << lc) + (v & cm);
+                        const lp_rsrc kc = buffer_rsrc(kcp, static_cast<unsigned>((((N - 1) << lc) + 1) * 8));
 #pragma unroll
                         for (int j = 0; j < R2; ++j) {
-                            const float2 k = kc[(i + j * F2::NB) << lc];
+                            const float2 k = bload2(kc, static_cast<unsigned>((i + j * F2::NB) << lc) * 8u);
                             x2[s][j] = CONJ ? cmulc(x2[s][j], k) : cmul(x2[s][j], k);
                         }
                     }
@@ -533,12 +542,12 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     };
 
     float2 x2[F2::S][R2];
-    forward(col, a.kh, x2);
+    forward(colp, a.kh, x2);
     if constexpr (SUM) {
         for (int t = 1; t < a.classes; ++t) {
             float2 z[F2::S][R2];
             __syncthreads();  // every thread is done reading the exchange buffer
-            forward(col + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
+            forward(colp + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
             if (act) {
 #pragma unroll
                 for (int s = 0; s < F2::S; ++s)
@@ -554,7 +563,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     float2 y1[I1::S][R1];
     if (act) {
         I1::load(y1, lds, tt, 0);
-        I1::template twiddle<true>(y1, a.tw_i1, tt);
+        I1::template twiddle<true>(y1, buffer_rsrc(a.tw_i1, I1::TABLE_BYTES), tt);
         I1::template butterfly<true>(y1, tt);
     }
     __syncthreads();
@@ -563,7 +572,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     if (act) {
         float2 y2[I2::S][R0];
         I2::load(y2, lds, tt, 0);
-        I2::template twiddle<true>(y2, a.tw_i2, tt);
+        I2::template twiddle<true>(y2, buffer_rsrc(a.tw_i2, I2::TABLE_BYTES), tt);
         I2::template butterfly<true>(y2, tt);
 #pragma unroll
         for (int s = 0; s < I2::S; ++s) {
@@ -572,7 +581,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                 for (int j = 0; j < R0; ++j) {
                     const int n = i + j * I2::NB;
-                    if (n < ny) col[n << lc] = y2[s][j];
+                    if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, y2[s][j]);
                 }
             }
         }
@@ -605,12 +614,13 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 {
     extern __shared__ float2 lds[];
     float *f = reinterpret_cast<float *>(lds);
+    constexpr bool JM = col_jmaj(N);
     using F0 = RegPass<N, R0, 1, TF, 1, 0>;
-    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
-    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0, JM>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0, JM>;
     using I0 = RegPass<N, R2, 1, TF, 1, 0>;
-    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
-    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2, JM>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0, JM>;
     const int tt = threadIdx.x;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
@@ -622,7 +632,11 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
         a.kh = it.kh;
     }
     const int lc = a.lc, cm = (1 << lc) - 1;
-    float2 *col = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
+    float2 *const colp = W + ((static_cast<int64_t>(v >> lc) * ny) << lc) + (v & cm);
+    // the column's ny stored values through a buffer resource: element n at
+    // byte 8 (n << lc), 32-bit offsets from a base held in scalar registers
+    const unsigned colb = static_cast<unsigned>((((ny - 1) << lc) + 1) * 8);
+    const lp_rsrc col = buffer_rsrc(colp, colb);
 
     // Eq. 9: product of the last forward pass's outputs (element u = i + j NB)
     // with the kernel spectrum
@@ -632,19 +646,21 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
             const int i = tt + s * TF;
             if (F2::valid(i)) {
                 if constexpr (FORM == 1) {
-                    const float *kq = static_cast<const float *>(kh) +
+                    const float *kqp = static_cast<const float *>(kh) +
                                       ((static_cast<int64_t>(v >> lc) * a.ku) << lc) + (v & cm);
+                    const lp_rsrc kq = buffer_rsrc(kqp, static_cast<unsigned>((((a.ku - 1) << lc) + 1) * 4));
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int u = i + j * F2::NB;
-                        xl[s][j] = cscale(xl[s][j], kq[((2 * u <= N) ? u : N - u) << lc]);
+                        xl[s][j] = cscale(xl[s][j], bload1(kq, static_cast<unsigned>(((2 * u <= N) ? u : N - u) << lc) * 4u));
                     }
                 } else {
-                    const float2 *kc = static_cast<const float2 *>(kh) +
+                    const float2 *kcp = static_cast<const float2 *>(kh) +
                                        ((static_cast<int64_t>(v >> lc) * N) << lc) + (v & cm);
+                    const lp_rsrc kc = buffer_rsrc(kcp, static_cast<unsigned>((((N - 1) << lc) + 1) * 8));
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
-                        const float2 k = kc[(i + j * F2::NB) << lc];
+                        const float2 k = bload2(kc, static_cast<unsigned>((i + j * F2::NB) << lc) * 8u);
                         xl[s][j] = CONJ ? cmulc(xl[s][j], k) : cmul(xl[s][j], k);
                     }
                 }
@@ -652,7 +668,8 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
         }
     };
 
-    auto forward = [&](const float2 *__restrict__ src, const void *kh, float2 (&xl)[F2::S][R2]) {
+    auto forward = [&](const float2 *srcp, const void *kh, float2 (&xl)[F2::S][R2]) {
+        const lp_rsrc src = buffer_rsrc(srcp, colb);
         float2 x0[F0::S][R0];
         if (act) {
 #pragma unroll
@@ -662,7 +679,8 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 #pragma unroll
                     for (int j = 0; j < R0; ++j) {
                         const int n = i + j * F0::NB;
-                        x0[s][j] = (n < ny) ? src[n << lc] : make_float2(0.f, 0.f);
+                        if (n < ny) x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
+                        else x0[s][j] = make_float2(0.f, 0.f);
                     }
                 }
             }
@@ -673,7 +691,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
         half_mid<F0, F1>(x0, x1, f, tt, act);
         if (act) {
             F1::template load_part<1>(x1, f, tt, 0);
-            F1::template twiddle<false>(x1, a.tw_f1, tt);
+            F1::template twiddle<false>(x1, buffer_rsrc(a.tw_f1, F1::TABLE_BYTES), tt);
             F1::template butterfly<false>(x1, tt);
         }
         __syncthreads();
@@ -681,7 +699,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
         half_mid<F1, F2>(x1, xl, f, tt, act);
         if (act) {
             F2::template load_part<1>(xl, f, tt, 0);
-            F2::template twiddle<false>(xl, a.tw_f2, tt);
+            F2::template twiddle<false>(xl, buffer_rsrc(a.tw_f2, F2::TABLE_BYTES), tt);
             F2::template butterfly<false>(xl, tt);
             multiply(xl, kh);
         }
@@ -696,19 +714,19 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 #pragma unroll
                 for (int j = 0; j < R0; ++j) {
                     const int n = i + j * I2::NB;
-                    if (n < ny) col[n << lc] = y[s][j];
+                    if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, y[s][j]);
                 }
             }
         }
     };
 
     float2 xl[F2::S][R2];
-    forward(col, a.kh, xl);
+    forward(colp, a.kh, xl);
     if constexpr (SUM) {
         for (int t = 1; t < a.classes; ++t) {
             float2 z[F2::S][R2];
             __syncthreads();  // every thread is done reading the exchange buffer
-            forward(col + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
+            forward(colp + t * a.w_stride, static_cast<const char *>(a.kh) + t * a.kh_stride, z);
             if (act) {
 #pragma unroll
                 for (int s = 0; s < F2::S; ++s)
@@ -724,7 +742,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
     half_mid<I0, I1>(xl, y1, f, tt, act);
     if (act) {
         I1::template load_part<1>(y1, f, tt, 0);
-        I1::template twiddle<true>(y1, a.tw_i1, tt);
+        I1::template twiddle<true>(y1, buffer_rsrc(a.tw_i1, I1::TABLE_BYTES), tt);
         I1::template butterfly<true>(y1, tt);
     }
     __syncthreads();
@@ -733,7 +751,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
     half_mid<I1, I2>(y1, y2, f, tt, act);
     if (act) {
         I2::template load_part<1>(y2, f, tt, 0);
-        I2::template twiddle<true>(y2, a.tw_i2, tt);
+        I2::template twiddle<true>(y2, buffer_rsrc(a.tw_i2, I2::TABLE_BYTES), tt);
         I2::template butterfly<true>(y2, tt);
         store_out(y2);
     }
@@ -771,12 +789,13 @@ template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ>
 __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_long_mid_reg(LongArgs a, ColRegArgs c)
 {
     extern __shared__ float2 lds[];
+    constexpr bool JM = col_jmaj(N);
     using F0 = RegPass<N, R0, 1, TF, 1, 0>;
-    using F1 = RegPass<N, R1, R0, TF, 1, R0>;
-    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0>;
+    using F1 = RegPass<N, R1, R0, TF, 1, R0, JM>;
+    using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0, JM>;
     using I0 = RegPass<N, R2, 1, TF, 1, 0>;
-    using I1 = RegPass<N, R1, R2, TF, 1, R2>;
-    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0>;
+    using I1 = RegPass<N, R1, R2, TF, 1, R2, JM>;
+    using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0, JM>;
     const int tt = threadIdx.x;
     const bool act = tt < TF;
     // the two columns of an interleaved group on one XCD (shared spectrum lines)
@@ -984,16 +1003,17 @@ static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int n
         const dim3 g(ncols, nitems), t(((c.tf + 63) / 64) * 64);
         const size_t lds = col_lds_bytes<I>();
         if (sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
+        const ColRegArgs &b = a;
         if (sum && form == 1)
-            launch_col<I, 1, false, true>(g, t, lds, s, W, a, items);
+            launch_col<I, 1, false, true>(g, t, lds, s, W, b, items);
         else if (sum)
-            launch_col<I, 2, false, true>(g, t, lds, s, W, a, items);
+            launch_col<I, 2, false, true>(g, t, lds, s, W, b, items);
         else if (form == 1)
-            launch_col<I, 1, false, false>(g, t, lds, s, W, a, items);
+            launch_col<I, 1, false, false>(g, t, lds, s, W, b, items);
         else if (conj_k)
-            launch_col<I, 2, true, false>(g, t, lds, s, W, a, items);
+            launch_col<I, 2, true, false>(g, t, lds, s, W, b, items);
         else
-            launch_col<I, 2, false, false>(g, t, lds, s, W, a, items);
+            launch_col<I, 2, false, false>(g, t, lds, s, W, b, items);
         return hipGetLastError();
     }
 }
@@ -1011,14 +1031,40 @@ hipError_t launch_cols_reg(float2 *W, const ColRegArgs &a, int idx, int ncols, i
 // ======================================================= register-resident rows
 namespace lp {
 
+typedef float lp_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void gstore4(gptr<float2> p, float2 a, float2 b)
+{
+    const lp_f4v v = {a.x, a.y, b.x, b.y};
+    *(gptr<lp_f4v>)p = v;
+}
+__device__ __forceinline__ void gload4(gptr<const float2> p, float2 &a, float2 &b)
+{
+    const lp_f4v v = *(gptr<const lp_f4v>)p;
+    a = make_float2(v.x, v.y);
+    b = make_float2(v.z, v.w);
+}
+
+// Staged intermediate of B consecutive rows (row0 = tile * B, B even or 1):
+// spectrum column k of row row0 + b at lds[k * B + b], 0 <= k <= M + 1 (the
+// last column is the pad of the two-column interleave when M + 1 is odd).
+// In HBM the pair of columns (2p, 2p + 1) of rows row0 .. row0 + B - 1 is one
+// run of 16 B bytes: chunk c = p B + b is row b's 16 bytes at
+// ((p ny + row0 + b) << 1).
+template <int M, int B>
+struct RowStage {
+    static constexpr int NCHUNK = ((M + 2) / 2) * B;
+    template <int NT>
+    static constexpr int per_thread() { return (NCHUNK + NT - 1) / NT; }
+};
+
 // Row z[n] = x[2n] + i x[2n+1] of the zero-padded map (columns >= nx, rows
 // >= ny are zero).
 template <bool EVEN_NX>
-__device__ __forceinline__ float2 load_pair(const float *__restrict__ src, int n, int nx, bool rv)
+__device__ __forceinline__ float2 load_pair(gptr<const float> src, int n, int nx, bool rv)
 {
     const int c0 = 2 * n;
     if (!rv || c0 >= nx) return make_float2(0.f, 0.f);
-    if (EVEN_NX) return *reinterpret_cast<const float2 *>(src + c0);
+    if (EVEN_NX) return gload2(src + c0);
     return make_float2(src[c0], (c0 + 1 < nx) ? src[c0 + 1] : 0.f);
 }
 
@@ -1051,7 +1097,7 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // transformed, so its HBM reads overlap the arithmetic.  The code is straight
 // line (no loop) so that the DFT constants are not hoisted into registers
 // that stay live across iterations.
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__restrict__ Rm,
                                                              float2 *__restrict__ W, RowRegArgs a,
                                                              const BatchItem *__restrict__ items)
@@ -1062,6 +1108,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
+    static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
     const int tid0 = threadIdx.x;
     if (items) {
         const BatchItem &it = items[blockIdx.y];
@@ -1077,7 +1124,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     auto load_tile = [&](float2 (&x)[F0::S][R0], int tile, int tt, int b) {
         const int row = tile * B + b;
         const bool rv = row < a.ny;
-        const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
+        const gptr<const float> src = as_global(Rm) + static_cast<int64_t>(rv ? row : 0) * a.nx;
 #pragma unroll
         for (int s = 0; s < F0::S; ++s) {
             const int i = tt + s * TF;
@@ -1103,10 +1150,11 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
             F1::store(x1, lds, tt, b);
         }
         __syncthreads();
-        if (tt <= NB / 2) {
-            const int i1 = tt, i2 = NB - tt;
-            const bool two = (i2 != i1) && (i2 < NB);
-            float2 z1[R2], z2[R2];
+        const int i1 = tt, i2 = NB - tt;
+        const bool pairer = tt <= NB / 2;
+        const bool two = pairer && (i2 != i1) && (i2 < NB);
+        float2 z1[R2], z2[R2];
+        if (pairer) {
 #pragma unroll
             for (int j = 0; j < R2; ++j) z1[j] = lds[(i1 + j * NB) * B + b];
             if (i1 > 0) {
@@ -1121,30 +1169,73 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
                 for (int j = 1; j < R2; ++j) z2[j] = cmul(z2[j], a.tw_f2[i2 * (R2 - 1) + j - 1]);
                 dftc<R2, false>(z2);
             }
-            if (rv) {
-                // X[k] of this row at ((k / C) * ny + row) * C + k % C
-                const int lc = a.lc, cm = (1 << lc) - 1;
-                float2 *dst = W + (static_cast<int64_t>(row) << lc);
-                auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
+        }
+        if constexpr (STG) {
+            // spectrum X[k] of the tile's rows into the exchange buffer (every
+            // thread has read its last-pass inputs), then out in 16-byte chunks
+            __syncthreads();
+            if (pairer) {
                 if (i1 == 0) {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k = j * NB;
-                        dst[at(k)] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+                        lds[k * B + b] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
                     }
-                    dst[at(M)] = r2c_split(z1[0], z1[0], a.rtw[M]);
+                    lds[M * B + b] = r2c_split(z1[0], z1[0], a.rtw[M]);
+                    lds[(M + 1) * B + b] = make_float2(0.f, 0.f);
                 } else if (!two) {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k = i1 + j * NB;
-                        dst[at(k)] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+                        lds[k * B + b] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < R2; ++j) {
                         const int k1 = i1 + j * NB, k2 = i2 + j * NB;
-                        dst[at(k1)] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
-                        dst[at(k2)] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                        lds[k1 * B + b] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
+                        lds[k2 * B + b] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                    }
+                }
+            }
+            __syncthreads();
+            using ST = RowStage<M, B>;
+            constexpr int NT = TF * B, PT = ST::template per_thread<NT>();
+            const int tid = tt * B + b;
+            const gptr<float2> dst = as_global(W) + (static_cast<int64_t>(tile * B) << 1);
+#pragma unroll
+            for (int q = 0; q < PT; ++q) {
+                const int c = tid + q * NT;
+                const int p = c / B, bb = c % B;
+                if ((ST::NCHUNK % NT == 0 || c < ST::NCHUNK) && tile * B + bb < a.ny)
+                    gstore4(dst + ((static_cast<int64_t>(p) * ny + bb) << 1), lds[(2 * p) * B + bb],
+                            lds[(2 * p + 1) * B + bb]);
+            }
+        } else if (pairer && rv) {
+            {
+                // X[k] of this row at ((k / C) * ny + row) * C + k % C
+                const int lc = a.lc, cm = (1 << lc) - 1;
+                const gptr<float2> dst = as_global(W) + (static_cast<int64_t>(row) << lc);
+                auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
+                if (i1 == 0) {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k = j * NB;
+                        gstore2(dst + at(k), r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]));
+                    }
+                    gstore2(dst + at(M), r2c_split(z1[0], z1[0], a.rtw[M]));
+                } else if (!two) {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k = i1 + j * NB;
+                        gstore2(dst + at(k), r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]));
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) {
+                        const int k1 = i1 + j * NB, k2 = i2 + j * NB;
+                        gstore2(dst + at(k1), r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]));
+                        gstore2(dst + at(k2), r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]));
                     }
                 }
             }
@@ -1194,7 +1285,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
 // NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
 // and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).  TPW tiles
 // per workgroup as in the forward kernel.
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX>
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
                                                              float *__restrict__ Sm, RowRegArgs a,
                                                              const BatchItem *__restrict__ items)
@@ -1205,6 +1296,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     constexpr int NB = M / R2;
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
+    static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
     const int tid0 = threadIdx.x;
     if (items) {
         const BatchItem &it = items[blockIdx.y];
@@ -1227,7 +1319,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         const bool rv = row >= a.keep0 && row < a.keep1;  // rows outside are not needed
         // X[k] of this row at ((k / C) * ny + row) * C + k % C
         const int lc = a.lc, cm = (1 << lc) - 1;
-        const float2 *src = W + (static_cast<int64_t>(rv ? row : 0) << lc);
+        const gptr<const float2> src = as_global(W) + (static_cast<int64_t>(rv ? row : 0) << lc);
         auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
 #pragma unroll
         for (int j = 0; j < R2; ++j) {
@@ -1236,13 +1328,51 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         }
         xm = make_float2(0.f, 0.f);
         if (rv && pairer) {
+            if constexpr (STG) {
+                // from the staged tile (stage_in, then a barrier)
 #pragma unroll
-            for (int j = 0; j < R2; ++j) xa[j] = src[at(i1 + j * NB)];
-            if (two) {
+                for (int j = 0; j < R2; ++j) xa[j] = lds[(i1 + j * NB) * B + b];
+                if (two) {
 #pragma unroll
-                for (int j = 0; j < R2; ++j) xb[j] = src[at(i2 + j * NB)];
+                    for (int j = 0; j < R2; ++j) xb[j] = lds[(i2 + j * NB) * B + b];
+                }
+                if (i1 == 0) xm = lds[M * B + b];
+            } else {
+#pragma unroll
+                for (int j = 0; j < R2; ++j) xa[j] = gload2(src + at(i1 + j * NB));
+                if (two) {
+#pragma unroll
+                    for (int j = 0; j < R2; ++j) xb[j] = gload2(src + at(i2 + j * NB));
+                }
+                if (i1 == 0) xm = gload2(src + at(M));
             }
-            if (i1 == 0) xm = src[at(M)];
+        }
+    };
+
+    // The tile's spectrum from HBM into the exchange buffer in 16-byte chunks
+    // (kept rows only); every chunk is loaded before any is written.
+    auto stage_in = [&](int tile) {
+        using ST = RowStage<M, B>;
+        constexpr int NT = TF * B, PT = ST::template per_thread<NT>();
+        const int tid = threadIdx.x;
+        const gptr<const float2> src = as_global(W) + (static_cast<int64_t>(tile * B) << 1);
+        float2 v0[PT], v1[PT];
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const int c = tid + q * NT;
+            const int p = c / B, bb = c % B, row = tile * B + bb;
+            v0[q] = v1[q] = make_float2(0.f, 0.f);
+            if ((ST::NCHUNK % NT == 0 || c < ST::NCHUNK) && row >= a.keep0 && row < a.keep1)
+                gload4(src + ((static_cast<int64_t>(p) * ny + bb) << 1), v0[q], v1[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            const int c = tid + q * NT;
+            const int p = c / B, bb = c % B;
+            if (ST::NCHUNK % NT == 0 || c < ST::NCHUNK) {
+                lds[(2 * p) * B + bb] = v0[q];
+                lds[(2 * p + 1) * B + bb] = v1[q];
+            }
         }
     };
 
@@ -1291,7 +1421,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         I2::template twiddle<true>(y2, a.tw_i2, tt);
         I2::template butterfly<true>(y2, tt);
         if (rv) {
-            float *dst = Sm + static_cast<int64_t>(row - a.keep0) * a.nx;
+            const gptr<float> dst = as_global(Sm) + static_cast<int64_t>(row - a.keep0) * a.nx;
 #pragma unroll
             for (int s = 0; s < I2::S; ++s) {
                 const int i = tt + s * TF;
@@ -1300,7 +1430,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
                     for (int j = 0; j < R0; ++j) {
                         const int c0 = 2 * (i + j * I2::NB);
                         if (EVEN_NX) {
-                            if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
+                            if (c0 < a.nx) gstore2(dst + c0, y2[s][j]);
                         } else {
                             if (c0 < a.nx) dst[c0] = y2[s][j].x;
                             if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
@@ -1319,7 +1449,14 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
         // a tile with no row to keep does nothing (uniform over the workgroup)
         if (t0 * B >= a.keep1 || (t0 + 1) * B <= a.keep0) return;
         float2 xa[R2], xb[R2], xm;
-        load_tile(xa, xb, xm, t0, tt0, b0);
+        if constexpr (STG) {
+            stage_in(t0);
+            __syncthreads();
+            load_tile(xa, xb, xm, t0, tt0, b0);
+            __syncthreads();  // the first pass rewrites the exchange buffer
+        } else {
+            load_tile(xa, xb, xm, t0, tt0, b0);
+        }
         transform(xa, xb, xm, t0, tt0, b0);
     } else if constexpr (TPW == 2) {
         const int t1 = t0 + G;
@@ -1400,7 +1537,7 @@ k_rows_r2c_half(const float *__restrict__ Rm, float2 *__restrict__ W, RowRegArgs
 
     float2 x0[F0::S][R0];
     {
-        const float *src = Rm + static_cast<int64_t>(rv ? row : 0) * a.nx;
+        const gptr<const float> src = as_global(Rm) + static_cast<int64_t>(rv ? row : 0) * a.nx;
 #pragma unroll
         for (int s = 0; s < F0::S; ++s) {
             const int i = tt + s * TF;
@@ -1458,27 +1595,27 @@ k_rows_r2c_half(const float *__restrict__ Rm, float2 *__restrict__ W, RowRegArgs
         if (rv) {
             // X[k] of this row at ((k / C) * ny + row) * C + k % C
             const int lc = a.lc, cm = (1 << lc) - 1;
-            float2 *dst = W + (static_cast<int64_t>(row) << lc);
+            const gptr<float2> dst = as_global(W) + (static_cast<int64_t>(row) << lc);
             auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
             if (i1 == 0) {
 #pragma unroll
                 for (int j = 0; j < R2; ++j) {
                     const int k = j * NB;
-                    dst[at(k)] = r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]);
+                    gstore2(dst + at(k), r2c_split(z1[j], z1[(R2 - j) % R2], a.rtw[k]));
                 }
-                dst[at(M)] = r2c_split(z1[0], z1[0], a.rtw[M]);
+                gstore2(dst + at(M), r2c_split(z1[0], z1[0], a.rtw[M]));
             } else if (!two) {
 #pragma unroll
                 for (int j = 0; j < R2; ++j) {
                     const int k = i1 + j * NB;
-                    dst[at(k)] = r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]);
+                    gstore2(dst + at(k), r2c_split(z1[j], z1[R2 - 1 - j], a.rtw[k]));
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < R2; ++j) {
                     const int k1 = i1 + j * NB, k2 = i2 + j * NB;
-                    dst[at(k1)] = r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]);
-                    dst[at(k2)] = r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]);
+                    gstore2(dst + at(k1), r2c_split(z1[j], z2[R2 - 1 - j], a.rtw[k1]));
+                    gstore2(dst + at(k2), r2c_split(z2[j], z1[R2 - 1 - j], a.rtw[k2]));
                 }
             }
         }
@@ -1531,15 +1668,15 @@ k_rows_c2r_half(const float2 *__restrict__ W, float *__restrict__ Sm, RowRegArgs
         }
         if (rv) {
             const int lc = a.lc, cm = (1 << lc) - 1;
-            const float2 *src = W + (static_cast<int64_t>(row) << lc);
+            const gptr<const float2> src = as_global(W) + (static_cast<int64_t>(row) << lc);
             auto at = [&](int k) { return ((static_cast<int64_t>(k >> lc) * ny) << lc) + (k & cm); };
 #pragma unroll
-            for (int j = 0; j < R2; ++j) xa[j] = src[at(i1 + j * NB)];
+            for (int j = 0; j < R2; ++j) xa[j] = gload2(src + at(i1 + j * NB));
             if (two) {
 #pragma unroll
-                for (int j = 0; j < R2; ++j) xb[j] = src[at(i2 + j * NB)];
+                for (int j = 0; j < R2; ++j) xb[j] = gload2(src + at(i2 + j * NB));
             }
-            if (i1 == 0) xm = src[at(M)];
+            if (i1 == 0) xm = gload2(src + at(M));
         }
         if (i1 == 0) {
 #pragma unroll
@@ -1591,7 +1728,7 @@ k_rows_c2r_half(const float2 *__restrict__ W, float *__restrict__ Sm, RowRegArgs
     I2::template twiddle<true>(y2, a.tw_i2, tt);
     I2::template butterfly<true>(y2, tt);
     if (rv) {
-        float *dst = Sm + static_cast<int64_t>(row - a.keep0) * a.nx;
+        const gptr<float> dst = as_global(Sm) + static_cast<int64_t>(row - a.keep0) * a.nx;
 #pragma unroll
         for (int s = 0; s < I2::S; ++s) {
             const int i = tt + s * TF;
@@ -1600,7 +1737,7 @@ k_rows_c2r_half(const float2 *__restrict__ W, float *__restrict__ Sm, RowRegArgs
                 for (int j = 0; j < R0; ++j) {
                     const int c0 = 2 * (i + j * I2::NB);
                     if (EVEN_NX) {
-                        if (c0 < a.nx) *reinterpret_cast<float2 *>(dst + c0) = y2[s][j];
+                        if (c0 < a.nx) gstore2(dst + c0, y2[s][j]);
                     } else {
                         if (c0 < a.nx) dst[c0] = y2[s][j].x;
                         if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;
@@ -1615,7 +1752,10 @@ template <int I>
 static constexpr size_t row_lds_bytes()
 {
     constexpr RowSpec c = kRowSpecs[I];
-    return static_cast<size_t>(xchg_words(c.m, c.r0, c.r2)) * c.b * (c.half ? 4 : 8);
+    // staged: the M + 1 spectrum columns of the tile plus the interleave's pad
+    constexpr int w = xchg_words(c.m, c.r0, c.r2);
+    constexpr int words = (c.stage && c.m + 2 > w) ? c.m + 2 : w;
+    return static_cast<size_t>(words) * c.b * (c.half ? 4 : 8);
 }
 
 template <int I, bool FWD, bool EVEN>
@@ -1628,9 +1768,9 @@ static const void *row_fn()
     else if constexpr (c.half)
         return reinterpret_cast<const void *>(&k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
     else if constexpr (FWD)
-        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0>);
     else
-        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN>);
+        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0>);
 }
 
 template <int I>
@@ -1659,16 +1799,16 @@ static hipError_t row_attrs()
 }
 
 template <int I>
-static hipError_t launch_row_from(int idx, const void *in, void *out, const RowRegArgs &a, bool fwd,
+static hipError_t launch_row_from(int idx, const void *in, void *out, const RowRegArgs &a0, bool fwd,
                                   hipStream_t s, const BatchItem *items, int nitems)
 {
     if constexpr (I >= kNumRowSpecs) {
         return hipErrorInvalidValue;
     } else {
-        if (idx != I) return launch_row_from<I + 1>(idx, in, out, a, fwd, s, items, nitems);
+        if (idx != I) return launch_row_from<I + 1>(idx, in, out, a0, fwd, s, items, nitems);
         constexpr RowSpec c = kRowSpecs[I];
         constexpr int PF = c.pf;
-        const int ntiles = (a.ny + c.b - 1) / c.b;
+        const int ntiles = (a0.ny + c.b - 1) / c.b;
         int groups = PF ? (ntiles + PF - 1) / PF : ntiles;
         if (PF == 0) {
             static int resident[kNumRowSpecs][2] = {};
@@ -1684,8 +1824,11 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
             }
             groups = ntiles < r ? ntiles : r;
         }
+        // the staged chunks are pairs of columns of the two-column interleave
+        if (c.stage && a0.lc != 1) return hipErrorInvalidValue;
         const dim3 g(groups, nitems), t(c.tf * c.b);
         const size_t lds = row_lds_bytes<I>();
+        const RowRegArgs &a = a0;
         const bool even = (a.nx % 2) == 0;
         if constexpr (c.half) {
             if (fwd) {
@@ -1702,13 +1845,15 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
         } else if (fwd) {
             const float *R = static_cast<const float *>(in);
             float2 *W = static_cast<float2 *>(out);
-            if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, R, W, a, items);
-            else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, R, W, a, items);
+            constexpr bool ST = c.stage != 0;
+            if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true, ST>), g, t, lds, s, R, W, a, items);
+            else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false, ST>), g, t, lds, s, R, W, a, items);
         } else {
             const float2 *W = static_cast<const float2 *>(in);
             float *S = static_cast<float *>(out);
-            if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true>), g, t, lds, s, W, S, a, items);
-            else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false>), g, t, lds, s, W, S, a, items);
+            constexpr bool ST = c.stage != 0;
+            if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, true, ST>), g, t, lds, s, W, S, a, items);
+            else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, PF, false, ST>), g, t, lds, s, W, S, a, items);
         }
         return hipGetLastError();
     }

@@ -367,11 +367,12 @@ class Plan:
     def variant_info(self, stage, k):
         """dict(radices, threads per transform, transforms per workgroup,
         min waves per SIMD, tiles per workgroup (0: persistent loop), length,
-        half exchange)."""
-        v = (ctypes.c_int * 9)()
-        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 9))
+        half exchange, staged)."""
+        v = (ctypes.c_int * 10)()
+        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 10))
         return {"radices": (v[0], v[1], v[2]), "threads": v[3], "per_group": v[4],
-                "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8])}
+                "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8]),
+                "staged": bool(v[9])}
 
     def timing(self, enable=True, every=1):
         """Stage events on every `every`-th call from the next one

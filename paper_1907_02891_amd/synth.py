@@ -145,10 +145,14 @@ ADJOINT = Workload("adjoint-2048x2048-psf801-p2880", 2048, 2048, 801, 801, 2880,
 # 5 x 5400 (>= n + k - 1 = 26000) lets the middle transforms use the 5400-point
 # register kernels (26244, the smallest 5-smooth size, has no specialised divisor)
 LARGE = Workload("large-24000x24000-psf2001-p27000", 24000, 24000, 2001, 2001, 27000, 27000, 0.5, 1006)
+# the grid of the paper's own maps (Sec. 3: 11920 x 11804 pixels of 404.4 m)
+# with the all-sky light-pollution-ratio kernel of Eqs. 12-13 out to its
+# 300 km validity range (742 px at 404.4 m: 1485 x 1485)
+PAPER = Workload("paper-11920x11804-alr1485-p13500", 11920, 11804, 1485, 1485, 13500, 13500, 0.4044, 1008)
 BATCHED_SEED = 1003
 CLASSES = Workload("classes-3x4096x4096-psf1201-p5400", 4096, 4096, 1201, 1201, 5400, 5400, 0.5, 1005)
 
-WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT, CLASSES, LARGE)}
+WORKLOADS = {w.name: w for w in (SMALL, COUNTRY, CONTINENTAL, ADJOINT, CLASSES, LARGE, PAPER)}
 
 
 def small_inputs(seed=SMALL.seed):
@@ -176,6 +180,18 @@ def continental_inputs(seed=CONTINENTAL.seed, n=16384, centres=None):
     rng = np.random.default_rng(seed)
     R = radiance_map(n, n, 6000, 0.20, (2.0, 40.0), rng, centres=centres)
     K = psf_powexp(1000, 2.5, 80.0, 0.5, radius_km=500.0)
+    return R, K
+
+
+def paper_inputs(seed=PAPER.seed, centres=None):
+    """The paper's map grid (Sec. 3), 11920 x 11804 pixels of 404.4 m, filled
+    with the city-cluster generator at the continental density (20%
+    background, 3150 blobs, sigma 2-40 px); the ALR kernel of Eqs. 12-13
+    cut at its 300 km validity range, 1485 x 1485.  `centres`: as in
+    radiance_map."""
+    rng = np.random.default_rng(seed)
+    R = radiance_map(PAPER.ny, PAPER.nx, 3150, 0.20, (2.0, 40.0), rng, centres=centres)
+    K = psf_alr(PAPER.ky // 2, PAPER.pitch_km, radius_km=300.0)
     return R, K
 
 

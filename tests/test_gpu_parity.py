@@ -293,6 +293,7 @@ VARIANT_CASES = [  # ny, nx, ky, kx, padding, symmetric
     (5, 17000, 3, 1201, (8, 18432), False), (17000, 5, 1201, 3, (18432, 8), True),
     (4500, 7, 301, 3, (4800, 8), False), (7, 4500, 3, 301, (8, 4800), True),
     (7, 26990, 3, 21, (8, 27000), False),
+    (12001, 5, 1401, 3, (13500, 8), True), (5, 12001, 3, 1401, (8, 13500), False),
 ]
 
 

@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # column variant (kernel name, FETCH_SIZE / WRITE_SIZE KiB per dispatch, VALU
 # wave-instructions), with the kernel-source hash they were taken on
 PMC_FILES = {"country": os.path.join(ROOT, "profiles", "pmc_cols_conv_country4096.txt"),
-             "continental": os.path.join(ROOT, "profiles", "pmc_cols_conv_continental16384.txt")}
+             "continental": os.path.join(ROOT, "profiles", "pmc_cols_conv_continental16384.txt"),
+             "paper": os.path.join(ROOT, "profiles", "pmc_cols_conv_paper11920x11804.txt")}
 KERNEL_SOURCES = ["paper_1907_02891_amd/csrc/lp_kernels.hip", "paper_1907_02891_amd/csrc/fft_lds.h",
                   "paper_1907_02891_amd/csrc/fft_reg.h", "paper_1907_02891_amd/csrc/lp_internal.h"]
 
@@ -382,7 +383,11 @@ def main():
         traffic, valu = None, None
     cols_s = head["stage_ms"][1] * 1e-3
     achieved = cols_b / cols_s / 1e9
-    col_kernel = "k_cols_reg" if head["kernels"] == "specialised" else "k_cols_conv"
+    col_kernel = "k_cols_conv (generic)"
+    if head["kernels"] == "specialised" and "columns" in head["variants"]:
+        ci = head["variants"]["columns"]["info"]
+        col_kernel = "%s<%d, radices %s>" % ("k_cols_half" if ci["half_exchange"] else "k_cols_reg", ci["length"],
+                                              "x".join(str(r) for r in ci["radices"]))
     if head["four_step"]:
         col_kernel = "k_long_fwd + k_long_mid + k_long_inv (four-step, P1 x P2 = %d x %d)" % head["column_split"]
         traffic, valu = None, None

@@ -368,8 +368,11 @@ int lp_batch_kernel_spectra(lp_batch *batch, const double *const *psfs);
 
 /* radiance[t], out[t]: device FP32 ny[t]*nx[t] per map (host array of device
  * pointers; out[t] may alias radiance[t]).  Per class and spectrum form, one
- * launch per stage covers every map; the whole sequence is captured once
- * into a HIP graph and replayed on the bound stream.  When the pointer set
+ * launch per stage covers every map (each class runs kernels specialised at
+ * compile time for its padded lengths, so the classes cannot share one
+ * launch); the whole sequence -- three launches per class and form, forked
+ * over parallel branches -- is captured once into a HIP graph and replayed
+ * on the bound stream as one graph launch.  When the pointer set
  * differs from the previous call the per-map device table is re-uploaded
  * (synchronising the stream); the graph reads it and is kept. */
 int lp_convolve_batched(lp_batch *batch, const float *const *radiance, float *const *out);
@@ -412,7 +415,10 @@ int lp_batch_group_count(const lp_batch *batch);
 int lp_batch_group_info(const lp_batch *batch, int g, int64_t *info, int n);
 int lp_batch_tile_group(const lp_batch *batch, int t);
 
-/* Per-class kernel variants (as lp_plan_set_variant); invalidates the graph. */
+/* Per-class kernel variants, as lp_plan_set_variant: LP_STAGE_ROWS selects
+ * the variant of both row stages, LP_STAGE_ROWS_INVERSE the inverse row
+ * stage alone, LP_STAGE_COLUMNS the column stage.  Invalidates the graph.
+ * Errors: LP_E_INVALID (class, stage or variant out of range). */
 int lp_batch_set_variant(lp_batch *batch, int g, int stage, int k);
 int lp_batch_get_variant(const lp_batch *batch, int g, int stage);
 

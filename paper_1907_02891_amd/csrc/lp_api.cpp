@@ -1132,6 +1132,7 @@ struct lp_batch {
     struct Group {
         int64_t py = 0, px = 0, m = 0, h = 0;
         int col_variant = 0, row_variant = 0, col_spec = -1, row_spec = -1;
+        int row_variant_inv = 0, row_spec_inv = -1;  // the inverse row stage's (may differ)
         std::vector<float> twc, twr, rtw;
         size_t twc_off[4] = {0, 0, 0, 0}, twr_off[4] = {0, 0, 0, 0};
         size_t twc_max = 2, twr_max = 2;
@@ -1191,10 +1192,22 @@ void batch_group_tables(lp_batch::Group &g)
 {
     g.col_spec = lp::col_spec_index(static_cast<int>(g.py), g.col_variant);
     g.row_spec = lp::row_spec_index(static_cast<int>(g.m), g.row_variant);
+    g.row_spec_inv = lp::row_spec_index(static_cast<int>(g.m), g.row_variant_inv);
     const lp::ColSpec c = lp::kColSpecs[g.col_spec];
-    const lp::RowSpec r = lp::kRowSpecs[g.row_spec];
     spec_tables(c.r0, c.r1, c.r2, c.jmaj != 0, &g.twc, g.twc_off);
-    spec_tables(r.r0, r.r1, r.r2, false, &g.twr, g.twr_off);
+    // forward tables of the forward row variant, inverse ones of the inverse
+    // variant, concatenated (as a plan's)
+    const lp::RowSpec f = lp::kRowSpecs[g.row_spec], i = lp::kRowSpecs[g.row_spec_inv];
+    size_t off_f[4], off_i[4];
+    std::vector<float> ti;
+    spec_tables(f.r0, f.r1, f.r2, false, &g.twr, off_f);
+    spec_tables(i.r0, i.r1, i.r2, false, &ti, off_i);
+    const size_t base = g.twr.size() / 2;
+    g.twr.insert(g.twr.end(), ti.begin(), ti.end());
+    g.twr_off[0] = off_f[0];
+    g.twr_off[1] = off_f[1];
+    g.twr_off[2] = base + off_i[2];
+    g.twr_off[3] = base + off_i[3];
 }
 
 void batch_destroy_graph(lp_batch *b)
@@ -1249,7 +1262,7 @@ hipError_t batch_launch_all(lp_batch *b, const hipStream_t *streams, int nstream
             if ((e = lp::launch_rows_r2c_reg(nullptr, nullptr, rr, g.row_spec, s, items, nit)) != hipSuccess ||
                 (e = lp::launch_cols_reg(nullptr, cr, g.col_spec, static_cast<int>(g.h), f == 0 ? 1 : 2, false,
                                          s, items, nit)) != hipSuccess ||
-                (e = lp::launch_rows_c2r_reg(nullptr, nullptr, rr, g.row_spec, s, items, nit)) != hipSuccess)
+                (e = lp::launch_rows_c2r_reg(nullptr, nullptr, rr, g.row_spec_inv, s, items, nit)) != hipSuccess)
                 return e;
         }
     }
@@ -1334,7 +1347,7 @@ static int batch_plan(lp_batch *b)
             }
             for (int k = 0; k < lp::row_spec_count(static_cast<int>(g.m)); ++k) {
                 const lp::RowSpec c = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(g.m), k)];
-                g.twr_max = std::max<size_t>(g.twr_max, 2 * spec_table_len(c.r0, c.r1, c.r2));
+                g.twr_max = std::max<size_t>(g.twr_max, 4 * spec_table_len(c.r0, c.r1, c.r2));  // two variants' tables
             }
             batch_group_tables(g);
             g.rtw.assign(2 * (g.m + 1), 0.f);
@@ -1731,9 +1744,10 @@ int lp_batch_set_variant(lp_batch *b, int g, int stage, int k)
     if (!b) return fail(LP_E_INVALID, "null batch");
     if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
     lp_batch::Group &gr = b->groups[g];
-    if (stage == LP_STAGE_ROWS) {
+    if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
         if (k < 0 || k >= lp::row_spec_count(static_cast<int>(gr.m))) return fail(LP_E_INVALID, "no row variant %d", k);
-        gr.row_variant = k;
+        if (stage == LP_STAGE_ROWS) gr.row_variant = k;
+        gr.row_variant_inv = k;
     } else if (stage == LP_STAGE_COLUMNS) {
         if (k < 0 || k >= lp::col_spec_count(static_cast<int>(gr.py))) return fail(LP_E_INVALID, "no column variant %d", k);
         gr.col_variant = k;
@@ -1748,8 +1762,10 @@ int lp_batch_set_variant(lp_batch *b, int g, int stage, int k)
 int lp_batch_get_variant(const lp_batch *b, int g, int stage)
 {
     if (!b || g < 0 || g >= static_cast<int>(b->groups.size())) return -1;
-    return stage == LP_STAGE_ROWS ? b->groups[g].row_variant
-                                  : stage == LP_STAGE_COLUMNS ? b->groups[g].col_variant : -1;
+    return stage == LP_STAGE_ROWS             ? b->groups[g].row_variant
+           : stage == LP_STAGE_ROWS_INVERSE ? b->groups[g].row_variant_inv
+           : stage == LP_STAGE_COLUMNS      ? b->groups[g].col_variant
+                                            : -1;
 }
 
 }  // extern "C"

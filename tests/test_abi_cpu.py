@@ -204,6 +204,16 @@ def test_batch_contract_errors():
     assert lib.lp_convolve_batched(b._b, fake, fake) == lp.LP_E_NOMEM
     assert lib.lp_batch_set_variant(b._b, 0, 7, 0) == lp.LP_E_INVALID
     assert lib.lp_batch_set_variant(b._b, 0, lp.STAGE_ROWS, 99) == lp.LP_E_INVALID
+    assert lib.lp_batch_set_variant(b._b, 0, lp.STAGE_ROWS_INVERSE, 99) == lp.LP_E_INVALID
+    # the inverse row stage alone, and both row stages together (a class of
+    # padded rows that have several row variants)
+    b2 = lp.Batch([(4000, 4000)], [0], [(1201, 1201)])
+    assert b2.groups[0]["row_variants"] > 1
+    assert lib.lp_batch_set_variant(b2._b, 0, lp.STAGE_ROWS_INVERSE, 1) == lp.LP_OK
+    assert lib.lp_batch_get_variant(b2._b, 0, lp.STAGE_ROWS_INVERSE) == 1
+    assert lib.lp_batch_get_variant(b2._b, 0, lp.STAGE_ROWS) == 0
+    assert lib.lp_batch_set_variant(b2._b, 0, lp.STAGE_ROWS, 0) == lp.LP_OK
+    assert lib.lp_batch_get_variant(b2._b, 0, lp.STAGE_ROWS_INVERSE) == 0
 
 
 def test_precision_modes_host_side():

@@ -127,11 +127,24 @@ def test_batch_variants(lp, torch):
                     if b.tile_group(t) == g:
                         check(outs[t], refs[t], f"class {g} stage {stage} variant {k} map {t}")
             b.set_variant(g, stage, 0)
+        # the two row directions of a class on different variants (each its own tables)
+        n = info["row_variants"]
+        for k in range(n if n > 1 else 0):
+            b.set_variant(g, lp.STAGE_ROWS, k)
+            b.set_variant(g, lp.STAGE_ROWS_INVERSE, (k + 1) % n)
+            assert b.variant(g, lp.STAGE_ROWS) == k and b.variant(g, lp.STAGE_ROWS_INVERSE) == (k + 1) % n
+            outs = [o.cpu().numpy() for o in b.convolve(xs)]
+            for t in range(len(maps)):
+                if b.tile_group(t) == g:
+                    check(outs[t], refs[t], f"class {g} rows fwd v{k} inv v{(k + 1) % n} map {t}")
+        b.set_variant(g, lp.STAGE_ROWS, 0)
 
 
+@pytest.mark.timeout(900)
 def test_batched_workload_sampled(lp, torch):
-    """64 tiles (sides 512..3072) x 3 bands, 4 kernels (1201^2): 64 sampled
-    pixels per map against the oracle."""
+    """64 tiles (sides 512..3072) x 3 bands, 4 kernels (1201^2): 256 sampled
+    pixels per tile-band against the oracle, and the full field of the
+    first band of the four smallest tiles."""
     tiles, psf_ids, psfs = synth.batched_inputs()
     shapes, ids, maps = [], [], []
     for t, bands in enumerate(tiles):
@@ -148,11 +161,18 @@ def test_batched_workload_sampled(lp, torch):
     rng = np.random.default_rng(301)
     got, ref = [], []
     for t, (m, o) in enumerate(zip(maps, outs)):
-        idx = rng.choice(m.size, 64, replace=False)
+        idx = rng.choice(m.size, 256, replace=False)
         got.append(o.reshape(-1)[torch.from_numpy(idx).cuda()].cpu().numpy())
         ref.append(oracle.conv_same_pixels(m, psfs[ids[t]], idx))
+        check(got[-1], ref[-1], f"batched map {t} {m.shape} (256 px)")
     got, ref = np.concatenate(got), np.concatenate(ref)
     check(got, ref, "batched workload sampled")
+    # full fields: band 0 of the four smallest tiles (maps 3 t)
+    smallest = sorted(range(len(tiles)), key=lambda t: tiles[t][0].size)[:4]
+    for t in smallest:
+        k = 3 * t
+        check(outs[k].cpu().numpy(), oracle.conv_same(maps[k], psfs[ids[k]]),
+              f"batched tile {t} band 0 {maps[k].shape} full field")
 
 
 @pytest.mark.parametrize("case", [(1180, 200, 201, 31, 100, 1080, 1440, 1200),   # whole halos: Py >= ny

@@ -301,14 +301,22 @@ void plan_long_columns(lp_plan *p)
         p->mid_spec = -1;
         return;
     }
+    // P2: the longest divisor with a register-resident middle kernel whose
+    // exchange buffer (at least 8 bytes per value) leaves room for two
+    // workgroups per CU; one workgroup per CU leaves the middle transforms
+    // latency-bound (27000 = 2 x 13500 ran its middle kernel 36% slower than
+    // 5 x 5400)
     int64_t p2 = 1;
     p->mid_spec = -1;
-    for (int64_t d = lp::kMaxColLen; d >= 2; --d)
-        if (p->py % d == 0 && p->py / d <= 4096 && lp::long_mid_spec(static_cast<int>(d)) >= 0) {
+    for (int64_t d = lp::kMaxColLen; d >= 2; --d) {
+        if (p->py % d != 0 || p->py / d > 4096 || 2 * 8 * d > lp::kLdsBytes) continue;
+        const int spec = lp::long_mid_spec(static_cast<int>(d));
+        if (spec >= 0) {
             p2 = d;
-            p->mid_spec = lp::long_mid_spec(static_cast<int>(d));
+            p->mid_spec = spec;
             break;
         }
+    }
     if (p->mid_spec < 0)
         for (int64_t d = lp::kMaxColLen; d >= 2; --d)
             if (p->py % d == 0) { p2 = d; break; }

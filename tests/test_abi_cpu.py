@@ -52,8 +52,11 @@ def test_create_rejects_oversize(shape):
 
 def _four_step_p2(n, cap):
     """P2 of the four-step split: the longest divisor with a column
-    specialisation (and P1 <= 4096), else the largest divisor within a tile."""
-    spec = [d for d in lp.spec_lengths()[0] if d <= cap and n % d == 0 and n // d <= 4096]
+    specialisation whose exchange buffer (8 bytes per value, 80 KiB at most:
+    two workgroups per CU) fits half the LDS (and P1 <= 4096), else the
+    largest divisor within a tile."""
+    spec = [d for d in lp.spec_lengths()[0]
+            if d <= cap and n % d == 0 and n // d <= 4096 and d * 8 <= 80 * 1024]
     return max(spec) if spec else max(d for d in range(2, cap + 1) if n % d == 0)
 
 
@@ -73,6 +76,13 @@ def test_four_step_column_split(shape):
     assert p.workspace_bytes >= (h + h % 2) * py * 8
     q = lp.Plan(4096, 4096, 1201, 1201)
     assert q.column_split == (1, q.padding[0])
+
+
+def test_four_step_split_prefers_two_workgroups_per_cu():
+    """27000 = 2 x 13500 = 5 x 5400: the 13500-point middle kernel's exchange
+    buffer (108 KiB) leaves one workgroup per CU, so the split is 5 x 5400."""
+    p = lp.Plan(24000, 24000, 2001, 2001, padding=(27000, 27000))
+    assert p.column_split == (5, 5400)
 
 
 def test_four_step_takes_one_class():

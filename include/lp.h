@@ -209,6 +209,17 @@ int lp_convolve_classes(lp_plan *plan, const float *const *radiance, float *out)
  * LP_E_INVALID for cls outside [0, T). */
 int lp_adjoint_class(lp_plan *plan, int cls, const float *grad_out, float *grad_in);
 
+/* Debug mode for reads of memory that no stage wrote.
+ * With enable != 0, every later call on the plan first fills its
+ * intermediate spectra (all classes, or the no-allocation scratch array) and
+ * the four-step scratch with a quiet NaN, by a kernel on the bound stream;
+ * an element that any stage read before a stage wrote it would turn the
+ * output into NaN, so a poisoned run must give the same bits as an ordinary
+ * one.  Costs one fill of the intermediate per call.  New plans start with
+ * it on when the environment variable LP_DEBUG_POISON is set and not "0".
+ * Errors: LP_E_INVALID. */
+int lp_plan_set_poison(lp_plan *plan, int enable);
+
 /* Per-stage timing with HIP events on the bound stream.  enable = N > 0
  * starts recording events around each of the three stages of every N-th
  * call that runs the path (lp_convolve, lp_adjoint, lp_convolve_classes,
@@ -408,6 +419,12 @@ int lp_batch_use_graph(lp_batch *batch, int enable);
  * bound stream; the runtime may then run classes side by side.  Invalidates
  * the graph.  Errors: LP_E_INVALID. */
 int lp_batch_set_graph_branches(lp_batch *batch, int n);
+
+/* Debug mode as lp_plan_set_poison: every later lp_convolve_batched first
+ * fills all the maps' intermediates with a quiet NaN (inside the captured
+ * graph).  New batches take it from LP_DEBUG_POISON.  Invalidates the graph.
+ * Errors: LP_E_INVALID. */
+int lp_batch_set_poison(lp_batch *batch, int enable);
 
 /* Classes: count; info for class g: {Py, Px, maps, row variants, column
  * variants, largest map row count} (up to n values); the class of map t. */

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(_HERE)
 LIB = os.path.join(_HERE, "liblp.so")
 SOURCES = ["csrc/lp_api.cpp", "csrc/lp_kernels.hip", "csrc/lp_reproject.hip", "csrc/lp_long.hip",
-           "csrc/lp_noalloc.hip"]
+           "csrc/lp_noalloc.hip", "csrc/lp_debug.hip"]
 
 # -packed-fp32-ops: keep hipcc from forming packed FP32 vector instructions.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -17,10 +17,22 @@
 
 static_assert(lp::kNoAllocBytes == LP_NOALLOC_MAX_BYTES, "scratch array size");
 
+namespace lp {
+hipError_t launch_poison(void *p, size_t bytes, hipStream_t s);  // lp_debug.hip
+}
+
 namespace {
 
 thread_local std::string g_err;
 thread_local int g_status = LP_OK;
+
+// LP_DEBUG_POISON set and not "0": new plans and batches NaN-fill their
+// intermediates before every call
+bool poison_default()
+{
+    const char *v = std::getenv("LP_DEBUG_POISON");
+    return v && *v && std::strcmp(v, "0") != 0;
+}
 
 void clear_error()
 {
@@ -245,6 +257,8 @@ struct lp_plan {
     hipStream_t stream = nullptr;
     bool bound = false;
     int form = LP_FORM_NONE;
+    // debug: NaN-fill the intermediates (and the four-step scratch) first
+    bool poison = false;
     // timing: events around the stages of every timing_every-th call (0: off)
     int timing_every = 0;
     int64_t timing_seen = 0;
@@ -523,6 +537,14 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     // the intermediate: the workspace's, or the scratch array given for it
     char *const wbase = w_scratch ? reinterpret_cast<char *>(w_scratch) : p->ws + p->off_w;
     float2 *W = reinterpret_cast<float2 *>(wbase);
+    if (p->poison) {
+        if ((e = lp::launch_poison(wbase, static_cast<size_t>(nin) * p->w_class, p->stream)) != hipSuccess)
+            return fail_hip(e, "poison fill");
+        if (p->long_cols &&
+            (e = lp::launch_poison(p->ws + p->off_t, static_cast<size_t>(p->nblk << p->logc) * p->py * 8, p->stream)) !=
+                hipSuccess)
+            return fail_hip(e, "poison fill");
+    }
     const lp::RowArgs ra = row_args(p);
     lp::ColArgs ca = col_args(p);
     ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
@@ -642,6 +664,7 @@ lp_plan *lp_plan_create(int64_t ny, int64_t nx, int64_t ky, int64_t kx, double p
         return nullptr;
     }
     p->ny = ny; p->nx = nx; p->ky = ky; p->kx = kx; p->pitch = pitch_km;
+    p->poison = poison_default();
     // default: the full linear extent n + k - 1 of Sec. 2.5; where that
     // exceeds the maximum, the input-sized window's n + floor(k/2)
     int64_t py = next_5smooth(ny + ky - 1, false);
@@ -1083,6 +1106,14 @@ int lp_plan_set_classes(lp_plan *p, int n)
 
 int lp_plan_classes(const lp_plan *p) { return p ? p->classes : -1; }
 
+int lp_plan_set_poison(lp_plan *p, int enable)
+{
+    clear_error();
+    if (!p) return fail(LP_E_INVALID, "null plan");
+    p->poison = enable != 0;
+    return LP_OK;
+}
+
 int lp_plan_timing(lp_plan *p, int enable)
 {
     clear_error();
@@ -1168,6 +1199,8 @@ struct lp_batch {
     hipStream_t stream = nullptr;
     bool bound = false, spectra = false;
     bool use_graph = true, graph_ok = false, tables_dirty = true;
+    bool poison = false;   // NaN-fill the intermediates [0, w_bytes) first
+    size_t w_bytes = 0;
     hipStream_t cap = nullptr;
     // graph branches: classes are independent (own intermediates and
     // spectra), so the captured graph forks them over kBranches streams
@@ -1283,9 +1316,10 @@ hipError_t batch_launch_all(lp_batch *b, const hipStream_t *streams, int nstream
 // graph holds independent per-class chains.
 hipError_t batch_capture_all(lp_batch *b)
 {
+    hipError_t e;
+    if (b->poison && (e = lp::launch_poison(b->ws, b->w_bytes, b->cap)) != hipSuccess) return e;
     const int nb = std::min<int>(b->branches, static_cast<int>(b->groups.size()));
     if (nb <= 1) return batch_launch_all(b, &b->cap, 1);
-    hipError_t e;
     for (int i = 0; i < nb; ++i) {
         if (!b->branch[i] && (e = hipStreamCreateWithFlags(&b->branch[i], hipStreamNonBlocking)) != hipSuccess) return e;
         if (!b->join[i] && (e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming)) != hipSuccess) return e;
@@ -1384,6 +1418,7 @@ static int batch_plan(lp_batch *b)
         off += align256(static_cast<size_t>(g.h) * ny[t] * 8);
     }
     wtotal = off;
+    b->w_bytes = wtotal;
     size_t scratch = 0;
     for (auto &g : b->groups)
         for (int p : g.psfs)
@@ -1470,6 +1505,7 @@ lp_batch *lp_batch_create_padded(int n_tiles, const int64_t *ny, const int64_t *
     }
     b->n = n_tiles;
     b->n_psf = n_psf;
+    b->poison = poison_default();
     b->pitch = pitch_km;
     b->ny.assign(ny, ny + n_tiles);
     b->keep0.assign(n_tiles, 0);
@@ -1641,6 +1677,8 @@ int lp_convolve_batched(lp_batch *b, const float *const *radiance, float *const 
         b->tables_dirty = false;
     }
     if (!b->use_graph) {
+        if (b->poison && (e = lp::launch_poison(b->ws, b->w_bytes, b->stream)) != hipSuccess)
+            return fail_hip(e, "poison fill");
         if ((e = batch_launch_all(b, &b->stream, 1)) != hipSuccess) return fail_hip(e, "batched launch");
         return LP_OK;
     }
@@ -1725,6 +1763,17 @@ int lp_batch_set_graph_branches(lp_batch *b, int n)
         b->branches = n;
         batch_destroy_graph(b);
         b->graph_ok = false;
+    }
+    return LP_OK;
+}
+
+int lp_batch_set_poison(lp_batch *b, int enable)
+{
+    clear_error();
+    if (!b) return fail(LP_E_INVALID, "null batch");
+    if (b->poison != (enable != 0)) {
+        b->poison = enable != 0;
+        batch_destroy_graph(b);
     }
     return LP_OK;
 }

@@ -76,6 +76,7 @@ _SIGS = {
     "lp_adjoint": ([_vp, _vp, _vp], ctypes.c_int),
     "lp_convolve_noalloc": ([_vp, _vp, _vp], ctypes.c_int),
     "lp_plan_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_plan_set_poison": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_plan_stage_ms": ([_vp, _dp, ctypes.c_int, _ip], ctypes.c_int),
     "lp_plan_shape": ([_vp, _ip, _ip], ctypes.c_int),
     "lp_plan_column_split": ([_vp, _i64p, _i64p], ctypes.c_int),
@@ -110,6 +111,7 @@ _SIGS = {
     "lp_batch_tile_group": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_batch_set_variant": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "lp_batch_set_graph_branches": ([_vp, ctypes.c_int], ctypes.c_int),
+    "lp_batch_set_poison": ([_vp, ctypes.c_int], ctypes.c_int),
     "lp_batch_get_variant": ([_vp, ctypes.c_int, ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -374,6 +376,10 @@ class Plan:
                 "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8]),
                 "staged": bool(v[9])}
 
+    def set_poison(self, enable=True):
+        """NaN-fill the intermediates before every call (lp_plan_set_poison)."""
+        _check(_lib.lp_plan_set_poison(self._p, int(bool(enable))))
+
     def timing(self, enable=True, every=1):
         """Stage events on every `every`-th call from the next one
         (lp_plan_timing); enable=False stops."""
@@ -491,6 +497,10 @@ class Batch:
 
     def set_variant(self, g, stage, k):
         _check(_lib.lp_batch_set_variant(self._b, int(g), int(stage), int(k)))
+
+    def set_poison(self, enable=True):
+        """NaN-fill every map's intermediate before each call (lp_batch_set_poison)."""
+        _check(_lib.lp_batch_set_poison(self._b, int(bool(enable))))
 
     def set_graph_branches(self, n):
         """Classes captured on n parallel graph branches (1 to 4)."""

@@ -394,3 +394,17 @@ def test_timing_interval_errors():
     assert lib.lp_plan_timing(p._p, -1) == lp.LP_E_INVALID
     assert lib.lp_plan_timing(p._p, 0) == lp.LP_OK
     assert lib.lp_plan_timing(None, 1) == lp.LP_E_INVALID
+
+
+def test_poison_setters():
+    """The debug fill is switched per plan and per batch; null handles are
+    LP_E_INVALID (no device work happens until a call runs the path)."""
+    lib = lp.raw()
+    assert lib.lp_plan_set_poison(None, 1) == lp.LP_E_INVALID
+    assert lib.lp_batch_set_poison(None, 1) == lp.LP_E_INVALID
+    p = lp.Plan(64, 48, 5, 7)
+    assert lib.lp_plan_set_poison(p._p, 1) == lp.LP_OK
+    assert lib.lp_plan_set_poison(p._p, 0) == lp.LP_OK
+    b = lp.Batch([(30, 40), (50, 20)], [0, 0], [(5, 5)])
+    assert lib.lp_batch_set_poison(b._b, 1) == lp.LP_OK
+    assert lib.lp_batch_set_poison(b._b, 0) == lp.LP_OK

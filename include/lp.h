@@ -108,8 +108,10 @@ int lp_plan_set_padding(lp_plan *plan, int64_t py, int64_t px);
 int lp_plan_get_padding(const lp_plan *plan, int64_t *py, int64_t *px);
 
 /* Device workspace the plan needs, in bytes (0 for a NULL plan): the
- * intermediate spectra of the map, the stored kernel spectrum and the FP32
- * twiddle tables.  Depends on the padding. */
+ * intermediate spectra of the map (two copies where the padded column
+ * length has specialised kernels, which write the column stage's result out
+ * of place), the stored kernel spectrum and the FP32 twiddle tables.
+ * Depends on the padding. */
 size_t lp_plan_workspace_bytes(const lp_plan *plan);
 
 /* Attach caller-owned device memory (dev_ws, >= lp_plan_workspace_bytes,
@@ -153,8 +155,9 @@ int lp_convolve(lp_plan *plan, const float *radiance, float *out);
  * lp_convolve with the intermediate spectra of the map held in a scratch
  * array that is part of the library itself (a device-resident array of
  * LP_NOALLOC_MAX_BYTES on each GPU the library runs on, kept until the
- * process ends) instead of in the bound workspace.  Same arguments, same
- * kernels, same result bits as lp_convolve; the plan must still be bound
+ * process ends) instead of in the bound workspace; the column stage then
+ * works in place in that array.  Same arguments, same kernels and
+ * arithmetic, same result bits as lp_convolve; the plan must still be bound
  * (its workspace holds the kernel spectrum and the twiddle tables) and its
  * workspace must be on the current device.  The call allocates nothing: no
  * hipMalloc, no allocating library routine.  Every call on one GPU shares
@@ -211,8 +214,9 @@ int lp_adjoint_class(lp_plan *plan, int cls, const float *grad_out, float *grad_
 
 /* Debug mode for reads of memory that no stage wrote.
  * With enable != 0, every later call on the plan first fills its
- * intermediate spectra (all classes, or the no-allocation scratch array) and
- * the four-step scratch with a quiet NaN, by a kernel on the bound stream;
+ * intermediate spectra (all classes and the column stage's output copy, or
+ * the no-allocation scratch array) and the four-step scratch with a quiet
+ * NaN, by a kernel on the bound stream;
  * an element that any stage read before a stage wrote it would turn the
  * output into NaN, so a poisoned run must give the same bits as an ordinary
  * one.  Costs one fill of the intermediate per call.  New plans start with

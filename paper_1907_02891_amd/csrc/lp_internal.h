@@ -205,6 +205,7 @@ struct ColRegArgs {
     const float2 *tw_f2; // exp(-2 pi i j k / N),            k < R0 R1,   1 <= j < R2
     const float2 *tw_i1; // exp(-2 pi i j k / (R2 R1)),      k < R2,      1 <= j < R1
     const float2 *tw_i2; // exp(-2 pi i j k / N),            k < R2 R1,   1 <= j < R0
+    float2 *wout;        // output intermediate, same layout (nullptr: in place over the input)
 };
 
 // One map of a batched launch: the specialised kernels take a device array of

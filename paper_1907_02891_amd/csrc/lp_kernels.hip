@@ -475,7 +475,9 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     // the column's ny stored values through a buffer resource: element n at
     // byte 8 (n << lc), 32-bit offsets from a base held in scalar registers
     const unsigned colb = static_cast<unsigned>((((ny - 1) << lc) + 1) * 8);
-    const lp_rsrc col = buffer_rsrc(colp, colb);
+    // the result goes to the same place in a.wout (out of place: the stores
+    // then never touch lines another column's workgroup still reads)
+    const lp_rsrc col = buffer_rsrc(a.wout ? a.wout + (colp - W) : colp, colb);
 
     // forward transform of one column and product with one spectrum, left in
     // x2 in the order the inverse's first pass takes it
@@ -636,7 +638,9 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
     // the column's ny stored values through a buffer resource: element n at
     // byte 8 (n << lc), 32-bit offsets from a base held in scalar registers
     const unsigned colb = static_cast<unsigned>((((ny - 1) << lc) + 1) * 8);
-    const lp_rsrc col = buffer_rsrc(colp, colb);
+    // the result goes to the same place in a.wout (out of place: the stores
+    // then never touch lines another column's workgroup still reads)
+    const lp_rsrc col = buffer_rsrc(a.wout ? a.wout + (colp - W) : colp, colb);
 
     // Eq. 9: product of the last forward pass's outputs (element u = i + j NB)
     // with the kernel spectrum

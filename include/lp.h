@@ -173,9 +173,13 @@ int lp_convolve(lp_plan *plan, const float *radiance, float *out);
 #define LP_NOALLOC_MAX_BYTES (128u << 20)
 int lp_convolve_noalloc(lp_plan *plan, const float *radiance, float *out);
 
-/* Transpose of lp_convolve (correlation with K: the same kernels with the
- * conjugate spectrum), for gradients: grad_in = C^T grad_out.  Device FP32
- * ny*nx in and out (may alias).  Same errors as lp_convolve. */
+/* Transpose of lp_convolve, for gradients: grad_in = C^T grad_out, where C
+ * is the discrete form of Eq. 7 that lp_convolve evaluates, so
+ * grad_in(p, q) = sum_{i,j} grad_out(i, j) K(i + cy - p, j + cx - q), a
+ * correlation with K.  By Eq. 9 it is the same three stages with the
+ * conjugate of the stored spectrum (the crop and the zero padding swap
+ * roles, which the implicit padding covers).  Device FP32 ny*nx in and out
+ * (may alias).  Same errors as lp_convolve. */
 int lp_adjoint(lp_plan *plan, const float *grad_out, float *grad_in);
 
 /* ------------------------------------------------------ source classes --
@@ -381,11 +385,14 @@ int lp_batch_bind(lp_batch *batch, void *dev_ws, size_t bytes, void *stream);
  * as lp_kernel_spectrum).  Synchronises. */
 int lp_batch_kernel_spectra(lp_batch *batch, const double *const *psfs);
 
-/* radiance[t], out[t]: device FP32 ny[t]*nx[t] per map (host array of device
+/* Eq. 7 for every map of the batch (each with its own kernel; summing maps
+ * of several source classes, Sec. 2.2 / Eq. 4, is lp_convolve_classes).
+ * radiance[t], out[t]: device FP32 ny[t]*nx[t] per map (host array of device
  * pointers; out[t] may alias radiance[t]).  Per class and spectrum form, one
- * launch per stage covers every map (each class runs kernels specialised at
- * compile time for its padded lengths, so the classes cannot share one
- * launch); the whole sequence -- three launches per class and form, forked
+ * launch per stage covers every map (the kernels are specialised at compile
+ * time for each padded length; launches merged across the classes of one
+ * length ran slower than these per-class chains, which let one class's
+ * column stage run beside another's row stages); the whole sequence -- three launches per class and form, forked
  * over parallel branches -- is captured once into a HIP graph and replayed
  * on the bound stream as one graph launch.  When the pointer set
  * differs from the previous call the per-map device table is re-uploaded

@@ -1245,11 +1245,31 @@ std::vector<int64_t> spec_lengths(bool columns)
     return v;
 }
 
+// A batch keeps a plain column-major intermediate (one column after
+// another), so its row variants are those that do not stage the two-column
+// interleave of single-map plans: variant k of a batch is the k-th of them.
+int batch_row_spec(int64_t m, int k)
+{
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i) {
+        const int idx = lp::row_spec_index(static_cast<int>(m), i);
+        if (lp::kRowSpecs[idx].stage == 0 && k-- == 0) return idx;
+    }
+    return -1;
+}
+
+int batch_row_count(int64_t m)
+{
+    int c = 0;
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i)
+        c += lp::kRowSpecs[lp::row_spec_index(static_cast<int>(m), i)].stage == 0;
+    return c;
+}
+
 void batch_group_tables(lp_batch::Group &g)
 {
     g.col_spec = lp::col_spec_index(static_cast<int>(g.py), g.col_variant);
-    g.row_spec = lp::row_spec_index(static_cast<int>(g.m), g.row_variant);
-    g.row_spec_inv = lp::row_spec_index(static_cast<int>(g.m), g.row_variant_inv);
+    g.row_spec = batch_row_spec(g.m, g.row_variant);
+    g.row_spec_inv = batch_row_spec(g.m, g.row_variant_inv);
     const lp::ColSpec c = lp::kColSpecs[g.col_spec];
     spec_tables(c.r0, c.r1, c.r2, c.jmaj != 0, &g.twc, g.twc_off);
     // forward tables of the forward row variant, inverse ones of the inverse
@@ -1803,7 +1823,7 @@ int lp_batch_group_info(const lp_batch *b, int g, int64_t *info, int n)
     if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
     const lp_batch::Group &gr = b->groups[g];
     const int64_t v[6] = {gr.py, gr.px, static_cast<int64_t>(gr.items.size()),
-                          lp::row_spec_count(static_cast<int>(gr.m)), lp::col_spec_count(static_cast<int>(gr.py)),
+                          batch_row_count(gr.m), lp::col_spec_count(static_cast<int>(gr.py)),
                           gr.max_ny};
     for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
     return LP_OK;
@@ -1818,7 +1838,7 @@ int lp_batch_set_variant(lp_batch *b, int g, int stage, int k)
     if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
     lp_batch::Group &gr = b->groups[g];
     if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
-        if (k < 0 || k >= lp::row_spec_count(static_cast<int>(gr.m))) return fail(LP_E_INVALID, "no row variant %d", k);
+        if (k < 0 || k >= batch_row_count(gr.m)) return fail(LP_E_INVALID, "no row variant %d", k);
         if (stage == LP_STAGE_ROWS) gr.row_variant = k;
         gr.row_variant_inv = k;
     } else if (stage == LP_STAGE_COLUMNS) {

@@ -294,6 +294,48 @@ constexpr RowSpec kRowSpecs[] = {
     {1620, 180, 12, 9, 15, 2, 0, 1},
     {1800, 180, 12, 10, 15, 2, 0, 1},
     {2160, 180, 12, 12, 15, 2, 0, 1},
+    // four and eight rows per workgroup for the shorter rows of batched tiles
+    // and mid-size maps: 32- to 128-byte runs of the intermediate (staged:
+    // the two-column interleave of single-map plans; plain: the column-major
+    // intermediate of batches)
+    {600, 64, 12, 10, 5, 4, 0, 1, 0, 1},
+    {600, 64, 12, 10, 5, 4, 0, 1},
+    {600, 64, 12, 10, 5, 8, 0, 1, 0, 1},
+    {600, 64, 12, 10, 5, 8, 0, 1},
+    {720, 96, 8, 9, 10, 4, 0, 1, 0, 1},
+    {720, 96, 8, 9, 10, 4, 0, 1},
+    {720, 96, 8, 9, 10, 8, 0, 1, 0, 1},
+    {720, 96, 8, 9, 10, 8, 0, 1},
+    {800, 100, 8, 10, 10, 4, 0, 1, 0, 1},
+    {800, 100, 8, 10, 10, 4, 0, 1},
+    {800, 100, 8, 10, 10, 8, 0, 1, 0, 1},
+    {800, 100, 8, 10, 10, 8, 0, 1},
+    {960, 120, 8, 12, 10, 4, 0, 1, 0, 1},
+    {960, 120, 8, 12, 10, 4, 0, 1},
+    {960, 120, 8, 12, 10, 8, 0, 1, 0, 1},
+    {960, 120, 8, 12, 10, 8, 0, 1},
+    {900, 100, 10, 9, 10, 4, 0, 1, 0, 1},
+    {900, 100, 10, 9, 10, 4, 0, 1},
+    {900, 100, 10, 9, 10, 8, 0, 1, 0, 1},
+    {900, 100, 10, 9, 10, 8, 0, 1},
+    {1024, 128, 8, 8, 16, 4, 0, 1, 0, 1},
+    {1024, 128, 8, 8, 16, 4, 0, 1},
+    {1024, 128, 8, 8, 16, 8, 0, 1, 0, 1},
+    {1024, 128, 8, 8, 16, 8, 0, 1},
+    {1080, 120, 9, 10, 12, 4, 0, 1, 0, 1},
+    {1080, 120, 9, 10, 12, 4, 0, 1},
+    {1080, 120, 9, 10, 12, 8, 0, 1, 0, 1},
+    {1080, 120, 9, 10, 12, 8, 0, 1},
+    {1296, 108, 12, 12, 9, 4, 0, 1, 0, 1},
+    {1296, 108, 12, 12, 9, 4, 0, 1},
+    {1440, 128, 12, 12, 10, 4, 0, 1, 0, 1},
+    {1440, 128, 12, 12, 10, 4, 0, 1},
+    {1620, 180, 12, 9, 15, 4, 0, 1, 0, 1},
+    {1620, 180, 12, 9, 15, 4, 0, 1},
+    {1800, 180, 12, 10, 15, 4, 0, 1, 0, 1},
+    {1800, 180, 12, 10, 15, 4, 0, 1},
+    {2160, 180, 12, 12, 15, 4, 0, 1, 0, 1},
+    {2160, 180, 12, 12, 15, 4, 0, 1},
 };
 constexpr int kNumRowSpecs = sizeof kRowSpecs / sizeof kRowSpecs[0];
 

@@ -169,10 +169,37 @@ def length_sets(need_min, need_max, all_lengths):
     return out
 
 
+def tune_batch_rows(b, maps, ys, reps=3, warmup=1, verbose=False):
+    """Row variants of a bound batch, one choice per padded row length (all
+    classes of that length together), timed on the whole batch.  Returns
+    {row length: (chosen variant, ms per variant)}."""
+    by_px = {}
+    for g, info in enumerate(b.groups):
+        by_px.setdefault(info["padding"][1], []).append(g)
+    out = {}
+    for px, gs in sorted(by_px.items()):
+        n = b.groups[gs[0]]["row_variants"]
+        if n < 2:
+            continue
+        times = []
+        for k in range(n):
+            for g in gs:
+                b.set_variant(g, lp.STAGE_ROWS, k)
+            times.append(_time_batch(b, maps, ys, reps, warmup))
+        kbest = min(range(n), key=lambda k: times[k])
+        for g in gs:
+            b.set_variant(g, lp.STAGE_ROWS, kbest)
+        out[str(px)] = (kbest, [round(t, 4) for t in times])
+        if verbose:
+            print(f"tune batch: rows {px}: variant {kbest} of {times}", flush=True)
+    return out
+
+
 def autotune_batch(shapes, psf_ids, psfs, maps, *, pitch_km=0.5, reps=3, warmup=1, verbose=False):
     """Choose the padding classes of a batch: try restricted length sets
     (fewer, larger classes versus more padding), time each batch on the
-    given maps (device tensors), return (best Batch, report)."""
+    given maps (device tensors); on the fastest, choose the row variants per
+    padded row length and the graph branches; return (best Batch, report)."""
     import torch
     ly_all, lx_all = lp.spec_lengths()
     ky = [p.shape[0] for p in psfs]
@@ -201,8 +228,9 @@ def autotune_batch(shapes, psf_ids, psfs, maps, *, pitch_km=0.5, reps=3, warmup=
         else:
             b.close()
         torch.cuda.empty_cache()
-    # parallel class branches of the captured graph, on the chosen classes
     b = best[1]
+    report.append({"row_variants": tune_batch_rows(b, maps, ys, reps, warmup, verbose)})
+    # parallel class branches of the captured graph, on the chosen classes
     times = {}
     for n in (1, 2, 3, 4):
         b.set_graph_branches(n)

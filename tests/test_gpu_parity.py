@@ -294,6 +294,12 @@ VARIANT_CASES = [  # ny, nx, ky, kx, padding, symmetric
     (4500, 7, 301, 3, (4800, 8), False), (7, 4500, 3, 301, (8, 4800), True),
     (7, 26990, 3, 21, (8, 27000), False),
     (12001, 5, 1401, 3, (13500, 8), True), (5, 12001, 3, 1401, (8, 13500), False),
+    # row lengths of the batched tiles with two, four and eight rows per
+    # workgroup (row counts that leave a partial last tile)
+    (9, 1700, 3, 101, (10, 1800), True), (10, 1900, 3, 141, (12, 2048), False),
+    (11, 2000, 3, 121, (12, 2160), True), (13, 2400, 3, 181, (15, 2592), False),
+    (9, 3100, 3, 121, (10, 3240), True), (17, 3400, 3, 181, (18, 3600), False),
+    (9, 4100, 3, 201, (10, 4320), True),
 ]
 
 

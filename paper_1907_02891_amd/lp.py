@@ -234,6 +234,9 @@ class Plan:
         if workspace is None:
             dev = torch.device("cuda") if device is None else torch.device(device)
             workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        elif not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.dtype == torch.uint8
+                  and workspace.is_contiguous()):
+            raise ValueError("workspace must be a contiguous uint8 CUDA tensor")
         ptr = workspace.data_ptr()
         off = (-ptr) % 256
         self.workspace = workspace
@@ -466,13 +469,18 @@ class Batch:
         import torch
         rows = getattr(self, "_out_rows", {})
         oshapes = [(rows.get(t, sh[0]), sh[1]) for t, sh in enumerate(self.shapes)]
+        n = len(self.shapes)
+        if len(maps) != n:
+            raise ValueError(f"{len(maps)} maps for a batch of {n}")
         if outs is None:
             outs = [torch.empty(osh, dtype=torch.float32, device=m.device) for m, osh in zip(maps, oshapes)]
-        for m, o, sh, osh in zip(maps, outs, self.shapes, oshapes):
-            if (tuple(m.shape) != sh or tuple(o.shape) != osh or m.dtype != torch.float32 or o.dtype != torch.float32
-                    or not m.is_contiguous() or not o.is_contiguous()):
-                raise ValueError("bad map tensor")
-        n = len(self.shapes)
+        elif len(outs) != n:
+            raise ValueError(f"{len(outs)} outputs for a batch of {n}")
+        for t, (m, o, sh, osh) in enumerate(zip(maps, outs, self.shapes, oshapes)):
+            for x, want, what in ((m, sh, "map"), (o, osh, "output")):
+                if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float32
+                        and x.is_contiguous() and tuple(x.shape) == want):
+                    raise ValueError(f"{what} {t}: expected a contiguous float32 CUDA tensor of shape {want}")
         ins = (_vp * n)(*[m.data_ptr() for m in maps])
         ous = (_vp * n)(*[o.data_ptr() for o in outs])
         _ordered(self.stream, list(maps) + list(outs),

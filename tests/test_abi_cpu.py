@@ -226,6 +226,26 @@ def test_batch_contract_errors():
     assert lib.lp_batch_get_variant(b2._b, 0, lp.STAGE_ROWS_INVERSE) == 0
 
 
+def test_python_binding_rejects_host_and_mismatched_tensors():
+    """The binding checks tensors before anything reaches the library: host
+    tensors, a wrong count of maps or outputs, and a workspace that is not a
+    uint8 device tensor are errors (no host pointer is handed to a kernel)."""
+    import torch
+    b = lp.Batch([(60, 70), (30, 40)], [0, 0], [(11, 11)])
+    host = [torch.zeros(60, 70), torch.zeros(30, 40)]
+    with pytest.raises(ValueError, match="CUDA"):
+        b.convolve(host)
+    with pytest.raises(ValueError, match="1 maps for a batch of 2"):
+        b.convolve(host[:1])
+    with pytest.raises(ValueError, match="1 outputs for a batch of 2"):
+        b.convolve(host, host[:1])
+    p = lp.Plan(60, 70, 11, 11)
+    with pytest.raises(ValueError, match="CUDA"):
+        p.convolve(torch.zeros(60, 70))
+    with pytest.raises(ValueError, match="workspace"):
+        p.bind(workspace=torch.zeros(p.workspace_bytes + 256, dtype=torch.uint8))
+
+
 def test_precision_modes_host_side():
     lib = lp.raw()
     p = lp.Plan(16384, 16384, 2001, 2001)

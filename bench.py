@@ -230,6 +230,19 @@ def per_step_ms(fn, stream, steps):
     return [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
 
 
+def kernels_label(lp, plan):
+    """Which stages run specialised (register-resident) kernels: the split
+    forms have them for the rows of some lengths only (radix-16 pass on the
+    matrix cores); their column stage is generic."""
+    if plan.kernels != lp.KERNELS_SPECIALISED:
+        return "generic"
+    rows = plan.variant_count(lp.STAGE_ROWS) > 0
+    cols = plan.variant_count(lp.STAGE_COLUMNS) > 0 or (plan.column_split[0] > 1 and plan.precision == 0)
+    if rows and cols:
+        return "specialised"
+    return "specialised rows, generic columns" if rows else "specialised columns, generic rows"
+
+
 def bench_form(lp, torch, wl, K, x, args, precision, pad, stream, dev):
     """One arithmetic form on one plan: set-up (plan, spectrum, autotuner),
     warm-up, the timed steps, then the per-step and per-stage passes.
@@ -292,7 +305,7 @@ def bench_form(lp, torch, wl, K, x, args, precision, pad, stream, dev):
            "median_ms": round(float(np.median(steps_ms)), 5),
            "stage_ms": [round(v, 5) for v in stage_avg], "stage_calls": calls,
            "padding": [py, px], "form": plan.form, "shape": plan.shape,
-           "kernels": "specialised" if plan.kernels == lp.KERNELS_SPECIALISED else "generic",
+           "kernels": kernels_label(lp, plan),
            "four_step": plan.column_split[0] > 1, "column_split": plan.column_split,
            "col_variant": plan.variant(lp.STAGE_COLUMNS) if plan.kernels == lp.KERNELS_SPECIALISED and
            plan.variant_count(lp.STAGE_COLUMNS) > 0 else None,

@@ -501,6 +501,74 @@ __device__ __forceinline__ void mfma16_pass(float2 *buf, const FftPass &P, int l
     __syncthreads();
 }
 
+// One radix-16 pass on matrix cores inside a register-resident kernel:
+// ITEMS butterflies (a multiple of 16) over the NW waves of the workgroup,
+// 16 consecutive items per wave-chunk.  ld(w, j) returns input j of item w
+// (twiddled); st(w, k, v) takes output k.  As in mfma16_pass, lane l works on
+// item 16 chunk + l % 16 with inputs and outputs 4 (l / 16) .. 4 (l / 16) + 3.
+// AHEAD: how many chunks' inputs are in flight before a chunk's product (all
+// of a wave's chunks for inputs from HBM, so that their loads overlap; fewer
+// keeps fewer registers live).
+template <int SPLIT, bool INV, int ITEMS, int NW, int AHEAD, class LD, class ST>
+__device__ __forceinline__ void mfma16_items(const u4v_t *__restrict__ mf, LD ld, ST st)
+{
+    static_assert(SPLIT == 1 || SPLIT == 2, "split form");
+    static_assert(ITEMS % 16 == 0 && AHEAD >= 1, "whole chunks");
+    constexpr int CHUNKS = ITEMS / 16, CH = (CHUNKS + NW - 1) / NW;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane & 15, g = lane >> 4;
+    float x[CH][8];
+    // a chunk exists for this wave (uniform over the wave)
+    auto has = [&](int ch) { return CHUNKS % NW == 0 || wave + ch * NW < CHUNKS; };
+    auto fetch = [&](int ch) {
+        if (has(ch)) {
+            const int w = (wave + ch * NW) * 16 + c;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float2 v = ld(w, 4 * g + t);
+                x[ch][2 * t] = v.x;
+                x[ch][2 * t + 1] = v.y;
+            }
+        }
+    };
+    MfmaOps<SPLIT> ops;
+    ops.load(mf + (INV ? MfmaOps<SPLIT>::kVecs * 64 : 0), lane);
+    auto compute = [&](int ch) {
+        if (!has(ch)) return;
+        float unscale = 1.f / MfmaOps<SPLIT>::kMatScale;
+        if constexpr (SPLIT == 1) {
+            // one power-of-two scale per butterfly: its largest input into
+            // [2^14, 2^15)
+            float amax = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) amax = fmaxf(amax, fabsf(x[ch][q]));
+            amax = fmaxf(amax, __shfl_xor(amax, 16));
+            amax = fmaxf(amax, __shfl_xor(amax, 32));
+            int e = 0;
+            if (amax > 0.f) {
+                (void)frexpf(amax, &e);
+                e = 15 - e;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[ch][q] = ldexpf(x[ch][q], e);
+            unscale = ldexpf(unscale, -e);
+        }
+        f4v_t dre, dim;
+        ops.product(x[ch], dre, dim);
+        const int w = (wave + ch * NW) * 16 + c;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) st(w, 4 * g + t, make_float2(dre[t] * unscale, dim[t] * unscale));
+    };
+    constexpr int A = AHEAD < CH ? AHEAD : CH;
+#pragma unroll
+    for (int ch = 0; ch < A; ++ch) fetch(ch);
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch) {
+        if (ch + A < CH) fetch(ch + A);
+        compute(ch);
+    }
+}
+
 // Whole transform: all passes of `d` in order.  Entry and exit are barriers.
 // SPLIT 0: every pass on the vector ALU in FP32; SPLIT 1 or 2: radix-16
 // passes on matrix cores with split operands (the plan's factorisation

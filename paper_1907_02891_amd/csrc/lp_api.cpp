@@ -385,6 +385,36 @@ void choose_shape(lp_plan *p)
     p->t_rows = threads_for(p->m << logb);
 }
 
+// Row variants of a plan: the specialisations of its half row length whose
+// matrix-core flag matches the plan's precision (split-precision plans run
+// only variants with the radix-16 pass on the matrix cores, FP32 plans only
+// the others); variant k is the k-th of them.
+int plan_row_spec(const lp_plan *p, int k)
+{
+    const bool split = p->precision != LP_PRECISION_FP32;
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(p->m)); i < n; ++i) {
+        const int idx = lp::row_spec_index(static_cast<int>(p->m), i);
+        if ((lp::kRowSpecs[idx].mf != 0) == split && k-- == 0) return idx;
+    }
+    return -1;
+}
+
+int plan_row_count(const lp_plan *p)
+{
+    const bool split = p->precision != LP_PRECISION_FP32;
+    int c = 0;
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(p->m)); i < n; ++i)
+        c += (lp::kRowSpecs[lp::row_spec_index(static_cast<int>(p->m), i)].mf != 0) == split;
+    return c;
+}
+
+// the row stages run specialised kernels (the column stage's choice is
+// separate: its specialised kernels are FP32 only)
+bool rows_specialised(const lp_plan *p)
+{
+    return p->variant == 0 && p->row_spec >= 0 && p->row_spec_inv >= 0;
+}
+
 void build_spec_tables(lp_plan *p)
 {
     p->col_spec = lp::col_spec_index(static_cast<int>(p->py), p->col_variant);
@@ -399,8 +429,8 @@ void build_spec_tables(lp_plan *p)
     }
     // forward tables from the forward row variant, inverse ones from the
     // inverse variant, concatenated
-    p->row_spec = lp::row_spec_index(static_cast<int>(p->m), p->row_variant);
-    p->row_spec_inv = lp::row_spec_index(static_cast<int>(p->m), p->row_variant_inv);
+    p->row_spec = plan_row_spec(p, p->row_variant);
+    p->row_spec_inv = plan_row_spec(p, p->row_variant_inv);
     p->twr.clear();
     if (p->row_spec >= 0 && p->row_spec_inv >= 0) {
         const lp::RowSpec f = lp::kRowSpecs[p->row_spec], i = lp::kRowSpecs[p->row_spec_inv];
@@ -559,7 +589,7 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     lp::ColArgs ca = col_args(p);
     ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
     const bool spec_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
-    const bool rspec = p->row_spec >= 0 && p->row_spec_inv >= 0 && spec_ok;
+    const bool rspec = rows_specialised(p);
     lp::RowRegArgs rr{};
     if (rspec) {
         const float2 *twr = reinterpret_cast<const float2 *>(p->ws + p->off_twr);
@@ -573,6 +603,8 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         rr.tw_f2 = twr + p->twr_off[1];
         rr.tw_i1 = twr + p->twr_off[2];
         rr.tw_i2 = twr + p->twr_off[3];
+        rr.split = p->precision;
+        rr.mf = (p->precision != LP_PRECISION_FP32) ? p->ws + p->off_mf : nullptr;
     }
     for (int t = 0; t < nin; ++t) {
         float2 *Wt = reinterpret_cast<float2 *>(wbase + static_cast<size_t>(t) * p->w_class);
@@ -742,6 +774,9 @@ int lp_plan_set_precision(lp_plan *p, int mode)
     make_fft(p->m, &p->fx, &p->twx, mode);
     make_fft(p->py, &p->fy, &p->twy, mode);
     plan_long_columns(p);  // four-step columns stay FP32
+    // the variants are those of the new precision
+    p->row_variant = p->row_variant_inv = p->col_variant = 0;
+    build_spec_tables(p);
     return LP_OK;
 }
 
@@ -750,15 +785,18 @@ int lp_plan_precision(const lp_plan *p) { return p ? p->precision : -1; }
 int lp_plan_kernels(const lp_plan *p)
 {
     if (!p) return -1;
-    if (p->variant != 0 || p->precision != LP_PRECISION_FP32) return LP_KERNELS_GENERIC;
-    return (p->col_spec >= 0 || p->row_spec >= 0) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
+    if (p->variant != 0) return LP_KERNELS_GENERIC;
+    const bool cols = p->precision == LP_PRECISION_FP32 && p->col_spec >= 0;
+    return (cols || rows_specialised(p)) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
 }
 
 int lp_plan_variant_count(const lp_plan *p, int stage)
 {
     if (!p) return 0;
-    if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) return lp::row_spec_count(static_cast<int>(p->m));
-    if (stage == LP_STAGE_COLUMNS) return lp::col_spec_count(static_cast<int>(p->py));
+    if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) return plan_row_count(p);
+    // the specialised column kernels are FP32 only
+    if (stage == LP_STAGE_COLUMNS)
+        return p->precision == LP_PRECISION_FP32 ? lp::col_spec_count(static_cast<int>(p->py)) : 0;
     return 0;
 }
 
@@ -795,23 +833,23 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
 {
     clear_error();
     if (!p || !info) return fail(LP_E_INVALID, "null argument");
-    int v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) {
-        const int i = lp::row_spec_index(static_cast<int>(p->m), k);
+        const int i = plan_row_spec(p, k);
         if (i < 0) return fail(LP_E_INVALID, "no row variant %d", k);
         const lp::RowSpec c = lp::kRowSpecs[i];
-        const int t[10] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half, c.stage};
-        std::copy(t, t + 10, v);
+        const int t[11] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half, c.stage, c.mf};
+        std::copy(t, t + 11, v);
     } else if (stage == LP_STAGE_COLUMNS) {
         const int i = lp::col_spec_index(static_cast<int>(p->py), k);
         if (i < 0) return fail(LP_E_INVALID, "no column variant %d", k);
         const lp::ColSpec c = lp::kColSpecs[i];
-        const int t[10] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half, 0};
-        std::copy(t, t + 10, v);
+        const int t[11] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half, 0, 0};
+        std::copy(t, t + 11, v);
     } else {
         return fail(LP_E_INVALID, "unknown stage %d", stage);
     }
-    for (int i = 0; i < n && i < 10; ++i) info[i] = v[i];
+    for (int i = 0; i < n && i < 11; ++i) info[i] = v[i];
     return LP_OK;
 }
 
@@ -821,9 +859,7 @@ int lp_plan_shape(const lp_plan *p, int *cols_per_group, int *rows_per_group)
     if (!p) return fail(LP_E_INVALID, "null plan");
     if (cols_per_group) *cols_per_group = 1;
     if (rows_per_group)
-        *rows_per_group = (p->row_spec >= 0 && p->variant == 0 && p->precision == LP_PRECISION_FP32)
-                              ? lp::row_spec_rows(p->row_spec)
-                              : 1 << p->logb;
+        *rows_per_group = rows_specialised(p) ? lp::row_spec_rows(p->row_spec) : 1 << p->logb;
     return LP_OK;
 }
 
@@ -1246,13 +1282,14 @@ std::vector<int64_t> spec_lengths(bool columns)
 }
 
 // A batch keeps a plain column-major intermediate (one column after
-// another), so its row variants are those that do not stage the two-column
-// interleave of single-map plans: variant k of a batch is the k-th of them.
+// another) and computes in FP32, so its row variants are those that neither
+// stage the two-column interleave of single-map plans nor run a matrix-core
+// pass: variant k of a batch is the k-th of them.
 int batch_row_spec(int64_t m, int k)
 {
     for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i) {
         const int idx = lp::row_spec_index(static_cast<int>(m), i);
-        if (lp::kRowSpecs[idx].stage == 0 && k-- == 0) return idx;
+        if (lp::kRowSpecs[idx].stage == 0 && lp::kRowSpecs[idx].mf == 0 && k-- == 0) return idx;
     }
     return -1;
 }
@@ -1260,8 +1297,10 @@ int batch_row_spec(int64_t m, int k)
 int batch_row_count(int64_t m)
 {
     int c = 0;
-    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i)
-        c += lp::kRowSpecs[lp::row_spec_index(static_cast<int>(m), i)].stage == 0;
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i) {
+        const lp::RowSpec &r = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(m), i)];
+        c += r.stage == 0 && r.mf == 0;
+    }
     return c;
 }
 

@@ -250,6 +250,11 @@ struct RowSpec {
     // touches half the cache lines of per-element accesses; full exchange,
     // one tile per workgroup
     int stage = 0;
+    // mf: the radix-16 pass (R0 = 16: the forward's first pass, the
+    // inverse's last) runs on the matrix cores with split operands.  Such
+    // variants serve only the split-precision plans (whose form picks the
+    // kernel instance), and the other variants only the FP32 plans.
+    int mf = 0;
 };
 constexpr RowSpec kRowSpecs[] = {
     {2700, 128, 15, 15, 12, 2, 4, 1},
@@ -278,6 +283,11 @@ constexpr RowSpec kRowSpecs[] = {
     {9216, 256, 16, 24, 24, 2, 2, 1},
     {9216, 384, 24, 24, 16, 1, 0, 1},
     {9216, 384, 24, 24, 16, 2, 0, 1, 0, 1},
+    // the split-precision rows: radix 16 first and last, so that the forward
+    // transform's first pass and the inverse's last run on the matrix cores
+    // (16-36-16 keeps the paired real-to-complex pass at radix 16: no scratch)
+    {9216, 384, 16, 36, 16, 2, 0, 1, 0, 0, 1},
+    {9216, 384, 16, 24, 24, 2, 0, 1, 0, 0, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
     {1440, 120, 15, 12, 8, 2, 0, 1},
     {1440, 128, 12, 12, 10, 2, 3, 0},
@@ -345,6 +355,10 @@ struct RowRegArgs {
     int32_t keep0, keep1;  // inverse: rows [keep0, keep1) are written, row r at out + (r - keep0) nx
     const float2 *rtw;   // exp(-2 pi i k / Px), 0 <= k <= M
     const float2 *tw_f1, *tw_f2, *tw_i1, *tw_i2;  // as in ColRegArgs, for length M
+    // variants whose radix-16 pass runs on the matrix cores: the split form
+    // (LP_PRECISION_SPLIT_FP16 or _BF16) and its operand fragment table
+    int32_t split;
+    const void *mf;
 };
 
 // Nearest-neighbour reprojection (lp_reproject.hip).

@@ -1048,6 +1048,10 @@ __device__ __forceinline__ void gload4(gptr<const float2> p, float2 &a, float2 &
     b = make_float2(v.z, v.w);
 }
 
+// Chunks of a matrix-core first pass whose inputs are read from HBM before
+// the first product.
+constexpr int MF_AHEAD_HBM = 3;
+
 // Staged intermediate of B consecutive rows (row0 = tile * B, B even or 1):
 // spectrum column k of row row0 + b at lds[k * B + b], 0 <= k <= M + 1 (the
 // last column is the pad of the two-column interleave when M + 1 is odd).
@@ -1101,7 +1105,7 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // transformed, so its HBM reads overlap the arithmetic.  The code is straight
 // line (no loop) so that the DFT constants are not hoisted into registers
 // that stay live across iterations.
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false>
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false, int MF = 0>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__restrict__ Rm,
                                                              float2 *__restrict__ W, RowRegArgs a,
                                                              const BatchItem *__restrict__ items)
@@ -1113,6 +1117,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
+    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && !STG && (TF * B) % 64 == 0),
+                  "matrix-core first pass: radix 16, one tile per workgroup, whole waves");
     const int tid0 = threadIdx.x;
     if (items) {
         const BatchItem &it = items[blockIdx.y];
@@ -1142,8 +1148,26 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     auto transform = [&](float2 (&x0)[F0::S][R0], int tile, int tt, int b) {
         const int row = tile * B + b;
         const bool rv = row < a.ny;
-        F0::template butterfly<false>(x0, tt);
-        F0::store(x0, lds, tt, b);
+        if constexpr (MF != 0) {
+            // the radix-16 first pass on the matrix cores, straight from HBM:
+            // item w = (row tile*B + w / F0::NB, butterfly w % F0::NB), its
+            // outputs in the layout F0::store writes
+            const gptr<const float> src = as_global(Rm);
+            mfma16_items<MF, false, F0::NB * B, TF * B / 64, MF_AHEAD_HBM>(
+                static_cast<const u4v_t *>(a.mf),
+                [&](int w, int j) {
+                    const int bb = w / F0::NB, i = w % F0::NB, r = tile * B + bb;
+                    const bool ok = r < a.ny;
+                    return load_pair<EVEN_NX>(src + static_cast<int64_t>(ok ? r : 0) * a.nx, i + j * F0::NB, a.nx, ok);
+                },
+                [&](int w, int k, float2 v) {
+                    const int bb = w / F0::NB, i = w % F0::NB;
+                    lds[(i * lds_pitch(16) + k) * B + bb] = v;
+                });
+        } else {
+            F0::template butterfly<false>(x0, tt);
+            F0::store(x0, lds, tt, b);
+        }
         __syncthreads();
         {
             float2 x1[F1::S][R1];
@@ -1253,7 +1277,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     const int tt0 = tid0 / B, b0 = tid0 % B;
     if constexpr (TPW == 1) {
         float2 x0[F0::S][R0];
-        load_tile(x0, t0, tt0, b0);
+        if constexpr (MF == 0) load_tile(x0, t0, tt0, b0);
         transform(x0, t0, tt0, b0);
     } else if constexpr (TPW == 2) {
         const int t1 = t0 + G;
@@ -1289,7 +1313,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
 // NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
 // and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).  TPW tiles
 // per workgroup as in the forward kernel.
-template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false>
+template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false, int MF = 0>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
                                                              float *__restrict__ Sm, RowRegArgs a,
                                                              const BatchItem *__restrict__ items)
@@ -1301,6 +1325,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
+    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && !STG && (TF * B) % 64 == 0),
+                  "matrix-core last pass: radix 16, one tile per workgroup, whole waves");
     const int tid0 = threadIdx.x;
     if (items) {
         const BatchItem &it = items[blockIdx.y];
@@ -1420,6 +1446,32 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
             I1::store(y1, lds, tt, b);
         }
         __syncthreads();
+        if constexpr (MF != 0) {
+            // the radix-16 last pass on the matrix cores: item w = (row
+            // tile*B + w / I2::NB, butterfly i = w % I2::NB); output k is
+            // element i + k I2::NB of the row, written to HBM (the crop)
+            mfma16_items<MF, true, I2::NB * B, TF * B / 64, 1>(
+                static_cast<const u4v_t *>(a.mf),
+                [&](int w, int j) {
+                    const int bb = w / I2::NB, i = w % I2::NB;
+                    const float2 v = lds[(i + j * I2::NB) * B + bb];
+                    return j ? cmulc(v, a.tw_i2[i * (R0 - 1) + j - 1]) : v;
+                },
+                [&](int w, int k, float2 v) {
+                    const int bb = w / I2::NB, i = w % I2::NB, r = tile * B + bb;
+                    if (r >= a.keep0 && r < a.keep1) {
+                        const gptr<float> dst = as_global(Sm) + static_cast<int64_t>(r - a.keep0) * a.nx;
+                        const int c0 = 2 * (i + k * I2::NB);
+                        if (EVEN_NX) {
+                            if (c0 < a.nx) gstore2(dst + c0, v);
+                        } else {
+                            if (c0 < a.nx) dst[c0] = v.x;
+                            if (c0 + 1 < a.nx) dst[c0 + 1] = v.y;
+                        }
+                    }
+                });
+            return;
+        }
         float2 y2[I2::S][R0];
         I2::load(y2, lds, tt, b);
         I2::template twiddle<true>(y2, a.tw_i2, tt);
@@ -1762,19 +1814,25 @@ static constexpr size_t row_lds_bytes()
     return static_cast<size_t>(words) * c.b * (c.half ? 4 : 8);
 }
 
-template <int I, bool FWD, bool EVEN>
+// SPLIT: the split form of a variant with a matrix-core pass (1 or 2; 0 for
+// the other variants)
+template <int I, bool FWD, bool EVEN, int SPLIT = (kRowSpecs[I].mf ? 2 : 0)>
 static const void *row_fn()
 {
     constexpr RowSpec c = kRowSpecs[I];
     static_assert(!c.half || c.pf == 1, "half-exchange rows take one tile per workgroup");
+    static_assert(!c.mf || (!c.half && !c.stage && c.pf == 1), "matrix-core rows: full exchange, one tile");
+    static_assert((SPLIT != 0) == (c.mf != 0), "split form of a matrix-core variant");
     if constexpr (c.half && FWD)
         return reinterpret_cast<const void *>(&k_rows_r2c_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
     else if constexpr (c.half)
         return reinterpret_cast<const void *>(&k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
     else if constexpr (FWD)
-        return reinterpret_cast<const void *>(&k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0>);
+        return reinterpret_cast<const void *>(
+            &k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0, SPLIT>);
     else
-        return reinterpret_cast<const void *>(&k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0>);
+        return reinterpret_cast<const void *>(
+            &k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, c.pf, EVEN, c.stage != 0, SPLIT>);
 }
 
 template <int I>
@@ -1783,8 +1841,18 @@ static hipError_t row_attrs_from()
     if constexpr (I >= kNumRowSpecs) {
         return hipSuccess;
     } else {
-        const void *fns[] = {row_fn<I, true, true>(), row_fn<I, true, false>(), row_fn<I, false, true>(),
-                             row_fn<I, false, false>()};
+        constexpr int NS = kRowSpecs[I].mf ? 2 : 1;  // instances per direction and parity
+        const void *fns[4 * NS];
+        if constexpr (kRowSpecs[I].mf) {
+            const void *t[8] = {row_fn<I, true, true, 1>(), row_fn<I, true, false, 1>(), row_fn<I, false, true, 1>(),
+                                row_fn<I, false, false, 1>(), row_fn<I, true, true, 2>(), row_fn<I, true, false, 2>(),
+                                row_fn<I, false, true, 2>(), row_fn<I, false, false, 2>()};
+            std::copy(t, t + 8, fns);
+        } else {
+            const void *t[4] = {row_fn<I, true, true>(), row_fn<I, true, false>(), row_fn<I, false, true>(),
+                                row_fn<I, false, false>()};
+            std::copy(t, t + 4, fns);
+        }
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
             if (e != hipSuccess) return e;
@@ -1845,6 +1913,30 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
                 float *S = static_cast<float *>(out);
                 if (even) hipLaunchKernelGGL((k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, true>), g, t, lds, s, W, S, a, items);
                 else hipLaunchKernelGGL((k_rows_c2r_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, false>), g, t, lds, s, W, S, a, items);
+            }
+        } else if constexpr (c.mf) {
+            // the split form picks the instance
+            if (!a.mf || (a.split != 1 && a.split != 2)) return hipErrorInvalidValue;
+            if (fwd) {
+                const float *R = static_cast<const float *>(in);
+                float2 *W = static_cast<float2 *>(out);
+                if (a.split == 1) {
+                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 1>), g, t, lds, s, R, W, a, items);
+                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 1>), g, t, lds, s, R, W, a, items);
+                } else {
+                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 2>), g, t, lds, s, R, W, a, items);
+                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 2>), g, t, lds, s, R, W, a, items);
+                }
+            } else {
+                const float2 *W = static_cast<const float2 *>(in);
+                float *S = static_cast<float *>(out);
+                if (a.split == 1) {
+                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 1>), g, t, lds, s, W, S, a, items);
+                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 1>), g, t, lds, s, W, S, a, items);
+                } else {
+                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 2>), g, t, lds, s, W, S, a, items);
+                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 2>), g, t, lds, s, W, S, a, items);
+                }
             }
         } else if (fwd) {
             const float *R = static_cast<const float *>(in);

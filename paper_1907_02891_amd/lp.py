@@ -372,12 +372,12 @@ class Plan:
     def variant_info(self, stage, k):
         """dict(radices, threads per transform, transforms per workgroup,
         min waves per SIMD, tiles per workgroup (0: persistent loop), length,
-        half exchange, staged)."""
-        v = (ctypes.c_int * 10)()
-        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 10))
+        half exchange, staged, matrix core)."""
+        v = (ctypes.c_int * 11)()
+        _check(_lib.lp_plan_variant_info(self._p, int(stage), int(k), v, 11))
         return {"radices": (v[0], v[1], v[2]), "threads": v[3], "per_group": v[4],
                 "min_waves": v[5], "tiles_per_group": v[6], "length": v[7], "half_exchange": bool(v[8]),
-                "staged": bool(v[9])}
+                "staged": bool(v[9]), "matrix_core": bool(v[10])}
 
     def set_poison(self, enable=True):
         """NaN-fill the intermediates before every call (lp_plan_set_poison)."""

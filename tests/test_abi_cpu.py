@@ -251,12 +251,29 @@ def test_precision_modes_host_side():
     p = lp.Plan(16384, 16384, 2001, 2001)
     assert p.precision == lp.PRECISION_FP32 and p.kernels == lp.KERNELS_SPECIALISED
     ws = p.workspace_bytes
+    n_fp32 = p.variant_count(lp.STAGE_ROWS)
+    assert not any(p.variant_info(lp.STAGE_ROWS, k)["matrix_core"] for k in range(n_fp32))
     for mode in (lp.PRECISION_SPLIT_FP16, lp.PRECISION_SPLIT_BF16, lp.PRECISION_FP32):
         p.set_precision(mode)
         assert p.precision == mode
-        # the split forms run the generic kernels; the layout does not change
-        assert p.kernels == (lp.KERNELS_SPECIALISED if mode == lp.PRECISION_FP32 else lp.KERNELS_GENERIC)
+        # 9216-point rows have a specialisation with the radix-16 pass on the
+        # matrix cores: the split forms run it (and only such row variants);
+        # the layout does not change
+        assert p.kernels == lp.KERNELS_SPECIALISED
+        n = p.variant_count(lp.STAGE_ROWS)
+        infos = [p.variant_info(lp.STAGE_ROWS, k) for k in range(n)]
+        split = mode != lp.PRECISION_FP32
+        assert n >= 1 and all(i["matrix_core"] == split for i in infos)
+        if split:
+            assert all(i["radices"][0] == 16 for i in infos)
+        else:
+            assert n == n_fp32
         assert p.workspace_bytes == ws
+    # lengths with no matrix-core row variant: a split plan runs the generic
+    # kernels in every stage
+    q = lp.Plan(4096, 4096, 1201, 1201)
+    q.set_precision(lp.PRECISION_SPLIT_BF16)
+    assert q.variant_count(lp.STAGE_ROWS) == 0 and q.kernels == lp.KERNELS_GENERIC
     for bad in (-1, 3, 99):
         with pytest.raises(lp.LPError) as ei:
             p.set_precision(bad)

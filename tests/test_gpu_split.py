@@ -1,6 +1,8 @@
 """GPU parity of the split-precision transforms: radix-16 passes as dense
 32 x 32 real matrix products on the matrix cores, operands split into FP16
-hi + lo (power-of-two block scaling) or BF16 x1 + x2 + x3, FP32 accumulation.
+hi + lo (power-of-two block scaling) or BF16 x1 + x2 + x3, FP32 accumulation,
+in the generic LDS kernels and in the register-resident 9216-point row
+kernels.
 Same bar as the FP32 path (relative L2 <= 1e-5, max |error| <= 1e-5 max |S|
 against the FP64 oracle), plus a tighter check that the error stays at the
 FP32 path's level."""
@@ -32,7 +34,7 @@ def lp(torch):
 def run(lp, torch, R, K, padding, precision, adjoint=False):
     plan = lp.make_plan(K, *R.shape, padding=padding, precision=precision)
     assert plan.precision == precision
-    if precision:
+    if precision and plan.padding[1] != 18432:
         assert plan.kernels == lp.KERNELS_GENERIC
     x = torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda()
     y = plan.adjoint(x) if adjoint else plan.convolve(x)
@@ -93,6 +95,42 @@ def test_split_matches_fp32_level(lp, torch, case, mode):
     e32, m32 = errors(S32, ref, f"fp32 {case[:4]}")
     esp, msp = errors(Ssp, ref, f"split {mode} {case[:4]}")
     assert esp <= max(3 * e32, 1e-6) and msp <= max(3 * m32, 1e-6)
+
+
+# maps whose padded rows are 18432 long (half rows 9216 = 16 x 24 x 24): the
+# split forms run the register-resident row kernels with the radix-16 pass
+# (the forward's first, the inverse's last) on the matrix cores
+MF_ROWS = [  # ny, nx, ky, kx, symmetric kernel
+    (37, 18000, 5, 401, True),    # even width, an odd number of rows (ragged last tile)
+    (30, 17999, 7, 433, False),   # odd width: the last column pair is cropped to one
+]
+
+
+@pytest.mark.parametrize("mode", MODES.values(), ids=list(MODES))
+@pytest.mark.parametrize("case", MF_ROWS, ids=[f"{c[0]}x{c[1]}" for c in MF_ROWS])
+def test_split_matrix_core_rows(lp, torch, case, mode):
+    ny, nx, ky, kx, sym = case
+    rng = np.random.default_rng(ny + nx + mode)
+    R = synth.radiance_map(ny, nx, 6, 0.05, (2.0, 10.0), rng)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
+    plan = lp.make_plan(K, ny, nx, precision=mode)
+    assert plan.padding[1] == 18432 and plan.kernels == lp.KERNELS_SPECIALISED
+    for stage in (lp.STAGE_ROWS, lp.STAGE_ROWS_INVERSE):
+        info = plan.variant_info(stage, plan.variant(stage))
+        assert info["matrix_core"] and info["radices"][0] == 16, info
+    x = torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda()
+    S = plan.convolve(x).cpu().numpy()
+    A = plan.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
+    ref = oracle.conv_same(R, K)
+    e2, em = errors(S, ref, f"matrix-core rows {mode} {case[:4]}")
+    assert e2 <= TOL and em <= TOL
+    a2, am = errors(A, oracle.adjoint_same(G, K), f"matrix-core rows {mode} {case[:4]} adjoint")
+    assert a2 <= TOL and am <= TOL
+    # and at the FP32 path's error level
+    S32, _ = run(lp, torch, R, K, None, 0)
+    e32, m32 = errors(S32, ref, f"fp32 {case[:4]}")
+    assert e2 <= max(3 * e32, 1e-6) and em <= max(3 * m32, 1e-6)
 
 
 @pytest.mark.parametrize("mode", MODES.values(), ids=list(MODES))

@@ -259,8 +259,7 @@ int lp_plan_kernels(const lp_plan *plan);
  * transform, transforms per workgroup, persistence with register prefetch);
  * a plan starts on variant 0 of each stage.  lp_plan_variant_count: how many
  * exist for the plan's padded size and precision (0: none, the generic
- * kernel runs; always 0 for the column stage of a split-precision plan,
- * whose specialised column kernels would be FP32).
+ * kernel runs).
  * lp_plan_set_variant may be called at any time (after lp_plan_bind it
  * re-uploads the stage's twiddle tables and synchronises the stream).
  * lp_plan_variant_info writes up to n of {R0, R1, R2, threads per transform,
@@ -269,11 +268,11 @@ int lp_plan_kernels(const lp_plan *plan);
  * (1: the passes exchange real and imaginary parts through LDS separately,
  * halving the buffer so that twice as many workgroups fit on a CU), staged
  * (row stages: 1 if the intermediate moves between HBM and LDS in 16-byte
- * chunks of two spectrum columns), matrix core (row stages: 1 if the radix-16
- * pass R0 runs on the matrix cores in the plan's split form)}.  The row
- * variants of a split-precision plan are those with a matrix-core pass, and
- * those of an FP32 plan the others, so the count and numbering depend on
- * lp_plan_set_precision (which resets the row variants to 0).
+ * chunks of two spectrum columns), matrix core (1 if the radix-16 pass R0 runs
+ * on the matrix cores in the plan's split form)}.  The variants of a
+ * split-precision plan are those with a matrix-core pass, and those of an
+ * FP32 plan the others, so the count and numbering depend on
+ * lp_plan_set_precision (which resets every stage to variant 0).
  * LP_STAGE_ROWS selects the variant of both row stages (and reports the
  * forward one); LP_STAGE_ROWS_INVERSE the inverse row stage alone, so the
  * two directions may run different specialisations of the same length. */
@@ -307,13 +306,14 @@ int lp_plan_column_split(const lp_plan *plan, int64_t *p1, int64_t *p2);
  *   LP_PRECISION_SPLIT_BF16: x = x1 + x2 + x3 in BF16, six products (all
  *     terms of total order <= 4).
  * Both keep the dropped terms near 2^-22 of a butterfly's largest input, so
- * the result stays at FP32-level error.  A split plan runs the row stages
- * on a register-resident specialisation whose radix-16 pass is on the
- * matrix cores where the library has one for the half row length (9216: the
- * radix-16 pass is the forward's first and the inverse's last), else on the
- * generic LDS-staged kernels; its column stage runs the generic kernels
- * (the specialised column kernels are FP32 only).  Lengths without a factor
- * 16 get no matrix pass.  Set before lp_plan_bind (LP_E_STATE after);
+ * the result stays at FP32-level error.  A split plan runs each stage on a
+ * register-resident specialisation whose radix-16 pass is on the matrix
+ * cores where the library has one for the length (9216-point half rows and
+ * 18432-point columns: the radix-16 pass is the forward transform's first
+ * and the inverse's last), else on the generic LDS-staged kernels, which
+ * take every radix-16 pass of the length to the matrix cores (four-step
+ * columns keep FP32 middle transforms).  Lengths without a factor 16 get no
+ * matrix pass.  Set before lp_plan_bind (LP_E_STATE after);
  * unknown mode: LP_E_INVALID.  lp_plan_precision returns the mode (-1 for a
  * NULL plan). */
 enum { LP_PRECISION_FP32 = 0, LP_PRECISION_SPLIT_FP16 = 1, LP_PRECISION_SPLIT_BF16 = 2 };

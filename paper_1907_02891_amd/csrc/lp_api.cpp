@@ -408,8 +408,27 @@ int plan_row_count(const lp_plan *p)
     return c;
 }
 
-// the row stages run specialised kernels (the column stage's choice is
-// separate: its specialised kernels are FP32 only)
+// Column variants of a plan, filtered the same way.
+int plan_col_spec(const lp_plan *p, int k)
+{
+    const bool split = p->precision != LP_PRECISION_FP32;
+    for (int i = 0, n = lp::col_spec_count(static_cast<int>(p->py)); i < n; ++i) {
+        const int idx = lp::col_spec_index(static_cast<int>(p->py), i);
+        if ((lp::kColSpecs[idx].mf != 0) == split && k-- == 0) return idx;
+    }
+    return -1;
+}
+
+int plan_col_count(const lp_plan *p)
+{
+    const bool split = p->precision != LP_PRECISION_FP32;
+    int c = 0;
+    for (int i = 0, n = lp::col_spec_count(static_cast<int>(p->py)); i < n; ++i)
+        c += (lp::kColSpecs[lp::col_spec_index(static_cast<int>(p->py), i)].mf != 0) == split;
+    return c;
+}
+
+// the row stages run specialised kernels
 bool rows_specialised(const lp_plan *p)
 {
     return p->variant == 0 && p->row_spec >= 0 && p->row_spec_inv >= 0;
@@ -417,7 +436,7 @@ bool rows_specialised(const lp_plan *p)
 
 void build_spec_tables(lp_plan *p)
 {
-    p->col_spec = lp::col_spec_index(static_cast<int>(p->py), p->col_variant);
+    p->col_spec = plan_col_spec(p, p->col_variant);
     p->twc.clear();
     if (p->col_spec >= 0) {
         const lp::ColSpec c = lp::kColSpecs[p->col_spec];
@@ -588,7 +607,8 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
     const lp::RowArgs ra = row_args(p);
     lp::ColArgs ca = col_args(p);
     ca.kh = p->ws + p->off_kh + static_cast<size_t>(kh_class) * p->kh_class;
-    const bool spec_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
+    // the four-step middle kernels are FP32 register kernels
+    const bool mid_ok = p->variant == 0 && p->precision == LP_PRECISION_FP32;
     const bool rspec = rows_specialised(p);
     lp::RowRegArgs rr{};
     if (rspec) {
@@ -635,9 +655,9 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         mr.tw_i1 = twc + p->twc_off[2];
         mr.tw_i2 = twc + p->twc_off[3];
         if ((e = lp::launch_long_cols(W, la, static_cast<int>(p->h), p->form, adjoint, p->t_outer, p->t_mid,
-                                      p->stream, spec_ok ? p->mid_spec : -1, &mr)) != hipSuccess)
+                                      p->stream, mid_ok ? p->mid_spec : -1, &mr)) != hipSuccess)
             return fail_hip(e, "four-step column stage launch");
-    } else if (p->col_spec >= 0 && spec_ok) {
+    } else if (p->col_spec >= 0 && p->variant == 0) {
         lp::ColRegArgs cr{};
         const float2 *twc = reinterpret_cast<const float2 *>(p->ws + p->off_twc);
         cr.ny = static_cast<int32_t>(p->ny);
@@ -651,6 +671,8 @@ int run_path(lp_plan *p, const float *const *ins, int nin, float *out, bool adjo
         cr.tw_f2 = twc + p->twc_off[1];
         cr.tw_i1 = twc + p->twc_off[2];
         cr.tw_i2 = twc + p->twc_off[3];
+        cr.split = p->precision;
+        cr.mf = (p->precision != LP_PRECISION_FP32) ? p->ws + p->off_mf : nullptr;
         // out of place into the second intermediate, which the inverse rows
         // then read (the no-allocation call has only its scratch array)
         if (!w_scratch && p->w2_bytes > 0) {
@@ -786,7 +808,7 @@ int lp_plan_kernels(const lp_plan *p)
 {
     if (!p) return -1;
     if (p->variant != 0) return LP_KERNELS_GENERIC;
-    const bool cols = p->precision == LP_PRECISION_FP32 && p->col_spec >= 0;
+    const bool cols = p->col_spec >= 0;
     return (cols || rows_specialised(p)) ? LP_KERNELS_SPECIALISED : LP_KERNELS_GENERIC;
 }
 
@@ -794,9 +816,7 @@ int lp_plan_variant_count(const lp_plan *p, int stage)
 {
     if (!p) return 0;
     if (stage == LP_STAGE_ROWS || stage == LP_STAGE_ROWS_INVERSE) return plan_row_count(p);
-    // the specialised column kernels are FP32 only
-    if (stage == LP_STAGE_COLUMNS)
-        return p->precision == LP_PRECISION_FP32 ? lp::col_spec_count(static_cast<int>(p->py)) : 0;
+    if (stage == LP_STAGE_COLUMNS) return plan_col_count(p);
     return 0;
 }
 
@@ -841,10 +861,10 @@ int lp_plan_variant_info(const lp_plan *p, int stage, int k, int *info, int n)
         const int t[11] = {c.r0, c.r1, c.r2, c.tf, c.b, c.occ, c.pf, c.m, c.half, c.stage, c.mf};
         std::copy(t, t + 11, v);
     } else if (stage == LP_STAGE_COLUMNS) {
-        const int i = lp::col_spec_index(static_cast<int>(p->py), k);
+        const int i = plan_col_spec(p, k);
         if (i < 0) return fail(LP_E_INVALID, "no column variant %d", k);
         const lp::ColSpec c = lp::kColSpecs[i];
-        const int t[11] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half, 0, 0};
+        const int t[11] = {c.r0, c.r1, c.r2, c.tf, 1, c.occ, 1, c.n, c.half, 0, c.mf};
         std::copy(t, t + 11, v);
     } else {
         return fail(LP_E_INVALID, "unknown stage %d", stage);
@@ -1272,9 +1292,11 @@ std::vector<int64_t> spec_lengths(bool columns)
 {
     std::vector<int64_t> v;
     if (columns) {
-        for (int i = 0; i < lp::kNumColSpecs; ++i) v.push_back(lp::kColSpecs[i].n);
+        for (int i = 0; i < lp::kNumColSpecs; ++i)
+            if (!lp::kColSpecs[i].mf) v.push_back(lp::kColSpecs[i].n);
     } else {
-        for (int i = 0; i < lp::kNumRowSpecs; ++i) v.push_back(2 * static_cast<int64_t>(lp::kRowSpecs[i].m));
+        for (int i = 0; i < lp::kNumRowSpecs; ++i)
+            if (!lp::kRowSpecs[i].mf) v.push_back(2 * static_cast<int64_t>(lp::kRowSpecs[i].m));
     }
     std::sort(v.begin(), v.end());
     v.erase(std::unique(v.begin(), v.end()), v.end());
@@ -1294,6 +1316,24 @@ int batch_row_spec(int64_t m, int k)
     return -1;
 }
 
+// column variants of a batch: the FP32 ones
+int batch_col_spec(int64_t py, int k)
+{
+    for (int i = 0, n = lp::col_spec_count(static_cast<int>(py)); i < n; ++i) {
+        const int idx = lp::col_spec_index(static_cast<int>(py), i);
+        if (lp::kColSpecs[idx].mf == 0 && k-- == 0) return idx;
+    }
+    return -1;
+}
+
+int batch_col_count(int64_t py)
+{
+    int c = 0;
+    for (int i = 0, n = lp::col_spec_count(static_cast<int>(py)); i < n; ++i)
+        c += lp::kColSpecs[lp::col_spec_index(static_cast<int>(py), i)].mf == 0;
+    return c;
+}
+
 int batch_row_count(int64_t m)
 {
     int c = 0;
@@ -1306,7 +1346,7 @@ int batch_row_count(int64_t m)
 
 void batch_group_tables(lp_batch::Group &g)
 {
-    g.col_spec = lp::col_spec_index(static_cast<int>(g.py), g.col_variant);
+    g.col_spec = batch_col_spec(g.py, g.col_variant);
     g.row_spec = batch_row_spec(g.m, g.row_variant);
     g.row_spec_inv = batch_row_spec(g.m, g.row_variant_inv);
     const lp::ColSpec c = lp::kColSpecs[g.col_spec];
@@ -1862,7 +1902,7 @@ int lp_batch_group_info(const lp_batch *b, int g, int64_t *info, int n)
     if (g < 0 || g >= static_cast<int>(b->groups.size())) return fail(LP_E_INVALID, "no group %d", g);
     const lp_batch::Group &gr = b->groups[g];
     const int64_t v[6] = {gr.py, gr.px, static_cast<int64_t>(gr.items.size()),
-                          batch_row_count(gr.m), lp::col_spec_count(static_cast<int>(gr.py)),
+                          batch_row_count(gr.m), batch_col_count(gr.py),
                           gr.max_ny};
     for (int i = 0; i < n && i < 6; ++i) info[i] = v[i];
     return LP_OK;
@@ -1881,7 +1921,7 @@ int lp_batch_set_variant(lp_batch *b, int g, int stage, int k)
         if (stage == LP_STAGE_ROWS) gr.row_variant = k;
         gr.row_variant_inv = k;
     } else if (stage == LP_STAGE_COLUMNS) {
-        if (k < 0 || k >= lp::col_spec_count(static_cast<int>(gr.py))) return fail(LP_E_INVALID, "no column variant %d", k);
+        if (k < 0 || k >= batch_col_count(gr.py)) return fail(LP_E_INVALID, "no column variant %d", k);
         gr.col_variant = k;
     } else {
         return fail(LP_E_INVALID, "unknown stage %d", stage);

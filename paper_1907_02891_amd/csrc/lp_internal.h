@@ -148,6 +148,10 @@ struct ColSpec {
     // twiddles); 1: per twiddle, at (j - 1) P + k (one load instruction reads
     // a contiguous run across the lanes).  Chosen by measurement per length.
     int jmaj = 0;
+    // mf: the radix-16 pass (R0 = 16: the forward's first pass, the
+    // inverse's last) runs on the matrix cores with split operands; such
+    // variants serve only split-precision plans, the others only FP32 plans
+    int mf = 0;
 };
 constexpr ColSpec kColSpecs[] = {
     {5400, 360, 20, 18, 15, 5},
@@ -158,6 +162,9 @@ constexpr ColSpec kColSpecs[] = {
     {4800, 320, 20, 15, 16, 5},
     {18432, 768, 32, 24, 24, 6, 1, 1},
     {18432, 768, 32, 24, 24, 0, 0, 1},
+    // split precision: radix 16 first and last (matrix cores), full exchange
+    {18432, 576, 16, 32, 36, 0, 0, 1, 1},
+    {18432, 576, 16, 36, 32, 0, 0, 1, 1},
     {2880, 240, 16, 12, 15, 0},
     {2880, 240, 12, 16, 15, 0},
     {512, 64, 8, 8, 8, 0},
@@ -206,6 +213,10 @@ struct ColRegArgs {
     const float2 *tw_i1; // exp(-2 pi i j k / (R2 R1)),      k < R2,      1 <= j < R1
     const float2 *tw_i2; // exp(-2 pi i j k / N),            k < R2 R1,   1 <= j < R0
     float2 *wout;        // output intermediate, same layout (nullptr: in place over the input)
+    // variants whose radix-16 pass runs on the matrix cores: the split form
+    // (LP_PRECISION_SPLIT_FP16 or _BF16) and its operand fragment table
+    int32_t split;
+    const void *mf;
 };
 
 // One map of a batched launch: the specialised kernels take a device array of

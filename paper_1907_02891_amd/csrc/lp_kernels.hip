@@ -437,6 +437,10 @@ hipError_t set_kernel_attributes()
 
 namespace lp {
 
+// Chunks of a matrix-core first pass whose inputs are read from HBM before
+// the first product.
+constexpr int MF_AHEAD_HBM = 3;
+
 // One column per workgroup: forward transform (radices R0, R1, R2), spectrum
 // multiply in registers, inverse transform (radices R2, R1, R0; its first
 // pass consumes the forward's last-pass outputs straight from registers), and
@@ -446,12 +450,16 @@ namespace lp {
 // with the class's spectrum are repeated for each class t (intermediate
 // W + t w_stride, spectrum kh + t kh_stride bytes) and summed in registers
 // before the one inverse transform, whose result goes to class 0's column.
-template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ, bool SUM>
+// MF (1 or 2): the radix-16 pass R0 (the forward's first, the inverse's
+// last) runs on the matrix cores in that split form, reading the column from
+// HBM and writing it back.
+template <int N, int TF, int R0, int R1, int R2, int OCC, int FORM, bool CONJ, bool SUM, int MF = 0>
 __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_reg(float2 *__restrict__ W, ColRegArgs a,
                                                                          const BatchItem *__restrict__ items)
 {
     extern __shared__ float2 lds[];
     constexpr bool JM = col_jmaj(N);
+    static_assert(MF == 0 || (R0 == 16 && TF % 64 == 0), "matrix-core pass: radix 16, whole waves");
     using F0 = RegPass<N, R0, 1, TF, 1, 0>;
     using F1 = RegPass<N, R1, R0, TF, 1, R0, JM>;
     using F2 = RegPass<N, R2, R0 * R1, TF, 1, 0, JM>;
@@ -484,7 +492,17 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     auto forward = [&](const float2 *srcp, const void *kh, float2 (&x2)[F2::S][R2]) {
         const lp_rsrc src = buffer_rsrc(srcp, colb);
         float2 x0[F0::S][R0];
-        if (act) {
+        if constexpr (MF != 0) {
+            // item i = butterfly i of the column: inputs i + j NB (rows >= ny
+            // read as zero), outputs in the layout F0::store writes
+            mfma16_items<MF, false, F0::NB, TF / 64, MF_AHEAD_HBM>(
+                static_cast<const u4v_t *>(a.mf),
+                [&](int i, int j) {
+                    const int n = i + j * F0::NB;
+                    return (n < ny) ? bload2(src, static_cast<unsigned>(n << lc) * 8u) : make_float2(0.f, 0.f);
+                },
+                [&](int i, int k, float2 v) { lds[i * lds_pitch(16) + k] = v; });
+        } else if (act) {
 #pragma unroll
             for (int s = 0; s < F0::S; ++s) {
                 const int i = tt + s * TF;
@@ -571,7 +589,26 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     __syncthreads();
     if (act) I1::store(y1, lds, tt, 0);
     __syncthreads();
-    if (act) {
+    if constexpr (MF != 0) {
+        // item i = butterfly i: inputs i + j NB of the exchange buffer,
+        // twiddled as I2::twiddle does (P = R2 R1 = NB, so i mod P = i);
+        // output k is row i + k NB of the column
+        constexpr int P = R2 * R1;
+        const lp_rsrc tw = buffer_rsrc(a.tw_i2, I2::TABLE_BYTES);
+        mfma16_items<MF, true, I2::NB, TF / 64, 1>(
+            static_cast<const u4v_t *>(a.mf),
+            [&](int i, int j) {
+                const float2 v = lds[i + j * I2::NB];
+                if (j == 0) return v;
+                const unsigned t = JM ? static_cast<unsigned>((j - 1) * P + i) * 8u
+                                      : static_cast<unsigned>(i * (R0 - 1) + j - 1) * 8u;
+                return cmulc(v, bload2(tw, t));
+            },
+            [&](int i, int k, float2 v) {
+                const int n = i + k * I2::NB;
+                if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, v);
+            });
+    } else if (act) {
         float2 y2[I2::S][R0];
         I2::load(y2, lds, tt, 0);
         I2::template twiddle<true>(y2, buffer_rsrc(a.tw_i2, I2::TABLE_BYTES), tt);
@@ -888,18 +925,20 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, OCC) k_long_mid_reg(Lon
 
 // The specialisation the four-step middle kernel uses for a length: the
 // first full-exchange column variant of that length (-1: none).
+// the four-step middle transforms run FP32 register kernels: the first
+// full-exchange FP32 specialisation of the length
 int long_mid_spec(int n)
 {
     for (int i = 0; i < kNumColSpecs; ++i)
-        if (kColSpecs[i].n == n && !kColSpecs[i].half) return i;
+        if (kColSpecs[i].n == n && !kColSpecs[i].half && !kColSpecs[i].mf) return i;
     return -1;
 }
 
 static constexpr bool is_long_mid_spec(int I)
 {
     for (int i = 0; i < I; ++i)
-        if (kColSpecs[i].n == kColSpecs[I].n && !kColSpecs[i].half) return false;
-    return !kColSpecs[I].half;
+        if (kColSpecs[i].n == kColSpecs[I].n && !kColSpecs[i].half && !kColSpecs[i].mf) return false;
+    return !kColSpecs[I].half && !kColSpecs[I].mf;
 }
 
 template <int I>
@@ -957,14 +996,18 @@ static constexpr size_t col_lds_bytes()
     return static_cast<size_t>(xchg_words(kColSpecs[I].n, kColSpecs[I].r0, kColSpecs[I].r2)) * (kColSpecs[I].half ? 4 : 8);
 }
 
-template <int I, int FORM, bool CONJ, bool SUM = false>
+// SPLIT: the split form of a variant with a matrix-core pass (1 or 2; 0 for
+// the other variants)
+template <int I, int FORM, bool CONJ, bool SUM = false, int SPLIT = (kColSpecs[I].mf ? 2 : 0)>
 static const void *col_fn()
 {
     constexpr ColSpec c = kColSpecs[I];
+    static_assert(!c.mf || !c.half, "matrix-core columns: full exchange");
+    static_assert((SPLIT != 0) == (c.mf != 0), "split form of a matrix-core variant");
     if constexpr (c.half)
         return reinterpret_cast<const void *>(&k_cols_half<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
     else
-        return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>);
+        return reinterpret_cast<const void *>(&k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM, SPLIT>);
 }
 
 template <int I, int FORM, bool CONJ, bool SUM>
@@ -974,7 +1017,12 @@ static void launch_col(dim3 g, dim3 t, size_t lds, hipStream_t s, float2 *W, con
     constexpr ColSpec c = kColSpecs[I];
     if constexpr (c.half)
         hipLaunchKernelGGL((k_cols_half<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>), g, t, lds, s, W, a, items);
-    else
+    else if constexpr (c.mf) {
+        if (a.split == 1)
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM, 1>), g, t, lds, s, W, a, items);
+        else
+            hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM, 2>), g, t, lds, s, W, a, items);
+    } else
         hipLaunchKernelGGL((k_cols_reg<c.n, c.tf, c.r0, c.r1, c.r2, c.occ, FORM, CONJ, SUM>), g, t, lds, s, W, a, items);
 }
 
@@ -984,8 +1032,20 @@ static hipError_t col_attrs_from()
     if constexpr (I >= kNumColSpecs) {
         return hipSuccess;
     } else {
-        const void *fns[] = {col_fn<I, 1, false>(), col_fn<I, 2, false>(), col_fn<I, 2, true>(),
-                             col_fn<I, 1, false, true>(), col_fn<I, 2, false, true>()};
+        constexpr int NS = kColSpecs[I].mf ? 2 : 1;  // instances per form
+        const void *fns[5 * NS];
+        if constexpr (kColSpecs[I].mf) {
+            const void *t[10] = {col_fn<I, 1, false, false, 1>(), col_fn<I, 2, false, false, 1>(),
+                                 col_fn<I, 2, true, false, 1>(), col_fn<I, 1, false, true, 1>(),
+                                 col_fn<I, 2, false, true, 1>(), col_fn<I, 1, false, false, 2>(),
+                                 col_fn<I, 2, false, false, 2>(), col_fn<I, 2, true, false, 2>(),
+                                 col_fn<I, 1, false, true, 2>(), col_fn<I, 2, false, true, 2>()};
+            std::copy(t, t + 10, fns);
+        } else {
+            const void *t[5] = {col_fn<I, 1, false>(), col_fn<I, 2, false>(), col_fn<I, 2, true>(),
+                                col_fn<I, 1, false, true>(), col_fn<I, 2, false, true>()};
+            std::copy(t, t + 5, fns);
+        }
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
             if (e != hipSuccess) return e;
@@ -1007,6 +1067,8 @@ static hipError_t launch_col_from(int idx, float2 *W, const ColRegArgs &a, int n
         const dim3 g(ncols, nitems), t(((c.tf + 63) / 64) * 64);
         const size_t lds = col_lds_bytes<I>();
         if (sum && conj_k) return hipErrorInvalidValue;  // class sums are forward only
+        // a matrix-core variant needs its split form and fragment table
+        if (c.mf && (!a.mf || (a.split != 1 && a.split != 2))) return hipErrorInvalidValue;
         const ColRegArgs &b = a;
         if (sum && form == 1)
             launch_col<I, 1, false, true>(g, t, lds, s, W, b, items);
@@ -1047,10 +1109,6 @@ __device__ __forceinline__ void gload4(gptr<const float2> p, float2 &a, float2 &
     a = make_float2(v.x, v.y);
     b = make_float2(v.z, v.w);
 }
-
-// Chunks of a matrix-core first pass whose inputs are read from HBM before
-// the first product.
-constexpr int MF_AHEAD_HBM = 3;
 
 // Staged intermediate of B consecutive rows (row0 = tile * B, B even or 1):
 // spectrum column k of row row0 + b at lds[k * B + b], 0 <= k <= M + 1 (the

@@ -251,23 +251,28 @@ def test_precision_modes_host_side():
     p = lp.Plan(16384, 16384, 2001, 2001)
     assert p.precision == lp.PRECISION_FP32 and p.kernels == lp.KERNELS_SPECIALISED
     ws = p.workspace_bytes
-    n_fp32 = p.variant_count(lp.STAGE_ROWS)
-    assert not any(p.variant_info(lp.STAGE_ROWS, k)["matrix_core"] for k in range(n_fp32))
+    n_fp32 = {st: p.variant_count(st) for st in (lp.STAGE_ROWS, lp.STAGE_COLUMNS)}
+    for st, n in n_fp32.items():
+        assert n >= 1 and not any(p.variant_info(st, k)["matrix_core"] for k in range(n))
+    p.set_variant(lp.STAGE_COLUMNS, 1)
     for mode in (lp.PRECISION_SPLIT_FP16, lp.PRECISION_SPLIT_BF16, lp.PRECISION_FP32):
         p.set_precision(mode)
         assert p.precision == mode
-        # 9216-point rows have a specialisation with the radix-16 pass on the
-        # matrix cores: the split forms run it (and only such row variants);
-        # the layout does not change
+        # 9216-point rows and 18432-point columns have specialisations with
+        # the radix-16 pass on the matrix cores: the split forms run them (and
+        # only such variants), starting from variant 0; the layout does not
+        # change
         assert p.kernels == lp.KERNELS_SPECIALISED
-        n = p.variant_count(lp.STAGE_ROWS)
-        infos = [p.variant_info(lp.STAGE_ROWS, k) for k in range(n)]
         split = mode != lp.PRECISION_FP32
-        assert n >= 1 and all(i["matrix_core"] == split for i in infos)
-        if split:
-            assert all(i["radices"][0] == 16 for i in infos)
-        else:
-            assert n == n_fp32
+        for st in (lp.STAGE_ROWS, lp.STAGE_COLUMNS):
+            assert p.variant(st) == 0
+            n = p.variant_count(st)
+            infos = [p.variant_info(st, k) for k in range(n)]
+            assert n >= 1 and all(i["matrix_core"] == split for i in infos)
+            if split:
+                assert all(i["radices"][0] == 16 for i in infos)
+            else:
+                assert n == n_fp32[st]
         assert p.workspace_bytes == ws
     # lengths with no matrix-core row variant: a split plan runs the generic
     # kernels in every stage

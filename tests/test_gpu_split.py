@@ -1,8 +1,8 @@
 """GPU parity of the split-precision transforms: radix-16 passes as dense
 32 x 32 real matrix products on the matrix cores, operands split into FP16
 hi + lo (power-of-two block scaling) or BF16 x1 + x2 + x3, FP32 accumulation,
-in the generic LDS kernels and in the register-resident 9216-point row
-kernels.
+in the generic LDS kernels and in the register-resident 9216-point row and
+18432-point column kernels.
 Same bar as the FP32 path (relative L2 <= 1e-5, max |error| <= 1e-5 max |S|
 against the FP64 oracle), plus a tighter check that the error stays at the
 FP32 path's level."""
@@ -34,7 +34,7 @@ def lp(torch):
 def run(lp, torch, R, K, padding, precision, adjoint=False):
     plan = lp.make_plan(K, *R.shape, padding=padding, precision=precision)
     assert plan.precision == precision
-    if precision and plan.padding[1] != 18432:
+    if precision and 18432 not in plan.padding:
         assert plan.kernels == lp.KERNELS_GENERIC
     x = torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda()
     y = plan.adjoint(x) if adjoint else plan.convolve(x)
@@ -131,6 +131,59 @@ def test_split_matrix_core_rows(lp, torch, case, mode):
     S32, _ = run(lp, torch, R, K, None, 0)
     e32, m32 = errors(S32, ref, f"fp32 {case[:4]}")
     assert e2 <= max(3 * e32, 1e-6) and em <= max(3 * m32, 1e-6)
+
+
+# maps whose padded columns are 18432 long: the split forms run register-
+# resident column kernels with the radix-16 pass (the forward transform's
+# first, the inverse's last) on the matrix cores, every variant of them
+MF_COLS = [  # ny, nx, ky, kx, symmetric kernel
+    (18000, 37, 401, 5, True),    # real quadrant spectrum
+    (17999, 30, 433, 7, False),   # complex spectrum, odd height
+]
+
+
+@pytest.mark.parametrize("mode", MODES.values(), ids=list(MODES))
+@pytest.mark.parametrize("case", MF_COLS, ids=[f"{c[0]}x{c[1]}" for c in MF_COLS])
+def test_split_matrix_core_columns(lp, torch, case, mode):
+    ny, nx, ky, kx, sym = case
+    rng = np.random.default_rng(ny + nx + 10 * mode)
+    R = synth.radiance_map(ny, nx, 6, 0.05, (2.0, 10.0), rng)
+    K = sym_kernel(rng, ky, kx) if sym else rng.random((ky, kx))
+    G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
+    ref, aref = oracle.conv_same(R, K), oracle.adjoint_same(G, K)
+    plan = lp.make_plan(K, ny, nx, precision=mode)
+    assert plan.padding[0] == 18432 and plan.kernels == lp.KERNELS_SPECIALISED
+    assert plan.form == (lp.FORM_REAL_QUADRANT if sym else lp.FORM_COMPLEX)
+    x, g = (torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda() for a in (R, G))
+    S32, _ = run(lp, torch, R, K, None, 0)
+    e32, m32 = errors(S32, ref, f"fp32 {case[:4]}")
+    n = plan.variant_count(lp.STAGE_COLUMNS)
+    assert n >= 2
+    for k in range(n):
+        plan.set_variant(lp.STAGE_COLUMNS, k)
+        info = plan.variant_info(lp.STAGE_COLUMNS, k)
+        assert info["matrix_core"] and info["radices"][0] == 16, info
+        S = plan.convolve(x).cpu().numpy()
+        e2, em = errors(S, ref, f"matrix-core columns {mode} {case[:4]} variant {k}")
+        assert e2 <= TOL and em <= TOL
+        assert e2 <= max(3 * e32, 1e-6) and em <= max(3 * m32, 1e-6)
+        A = plan.adjoint(g).cpu().numpy()
+        a2, am = errors(A, aref, f"matrix-core columns {mode} {case[:4]} variant {k} adjoint")
+        assert a2 <= TOL and am <= TOL
+
+
+@pytest.mark.parametrize("mode", MODES.values(), ids=list(MODES))
+def test_split_matrix_core_columns_class_sum(lp, torch, mode):
+    """Eq. 4 with the split column kernels: two classes summed in registers."""
+    rng = np.random.default_rng(5 + mode)
+    ny, nx, ky, kx = 18100, 21, 301, 9
+    Rs = [synth.radiance_map(ny, nx, 4, 0.05, (2.0, 10.0), rng) for _ in range(2)]
+    Ks = [rng.random((ky, kx)) for _ in range(2)]
+    plan = lp.make_plan_classes(Ks, ny, nx, precision=mode)
+    assert plan.padding[0] == 18432 and plan.variant_info(lp.STAGE_COLUMNS, 0)["matrix_core"]
+    y = plan.convolve_classes([torch.from_numpy(np.ascontiguousarray(r, np.float32)).cuda() for r in Rs])
+    e2, em = errors(y.cpu().numpy(), oracle.conv_same_classes(Rs, Ks), f"matrix-core columns {mode} class sum")
+    assert e2 <= TOL and em <= TOL
 
 
 @pytest.mark.parametrize("mode", MODES.values(), ids=list(MODES))

@@ -63,6 +63,9 @@ CASES = [  # label, ny, nx, ky, kx, padding, symmetric kernel, kernels, precisio
     ("split FP16 on MFMA", 300, 260, 41, 41, (512, 512), True, "auto", "fp16x2"),
     ("split BF16 on MFMA, complex form", 300, 260, 41, 31, (512, 512), False, "auto", "bf16x3"),
     ("four-step columns 4 x 5400", 20000, 4, 1001, 3, None, True, "auto", "fp32"),
+    # register kernels with the radix-16 pass on the matrix cores
+    ("split BF16 matrix-core rows 9216", 37, 18000, 5, 401, None, True, "auto", "bf16x3"),
+    ("split FP16 matrix-core columns 18432, complex form", 18000, 37, 401, 5, None, False, "auto", "fp16x2"),
 ]
 
 

@@ -299,6 +299,7 @@ constexpr RowSpec kRowSpecs[] = {
     // (16-36-16 keeps the paired real-to-complex pass at radix 16; 16-24-24
     // pairs radix-24 butterflies and spills at this occupancy)
     {9216, 384, 16, 36, 16, 2, 0, 1, 0, 0, 1},
+    {9216, 384, 16, 36, 16, 2, 0, 1, 0, 1, 1},
     {1440, 128, 12, 12, 10, 2, 5, 1},
     {1440, 120, 15, 12, 8, 2, 0, 1},
     {1440, 128, 12, 12, 10, 2, 3, 0},

@@ -1177,7 +1177,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
-    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && !STG && (TF * B) % 64 == 0),
+    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && (TF * B) % 64 == 0),
                   "matrix-core first pass: radix 16, one tile per workgroup, whole waves");
     const int tid0 = threadIdx.x;
     if (items) {
@@ -1385,7 +1385,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
     static_assert(R0 * R1 * R2 == M && NB / 2 + 1 <= TF, "row specialisation");
     static_assert(TPW >= 0 && TPW <= 2, "tiles per workgroup");
     static_assert(!STG || TPW == 1, "staged rows take one tile per workgroup");
-    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && !STG && (TF * B) % 64 == 0),
+    static_assert(MF == 0 || (R0 == 16 && TPW == 1 && (TF * B) % 64 == 0),
                   "matrix-core last pass: radix 16, one tile per workgroup, whole waves");
     const int tid0 = threadIdx.x;
     if (items) {
@@ -1881,7 +1881,7 @@ static const void *row_fn()
 {
     constexpr RowSpec c = kRowSpecs[I];
     static_assert(!c.half || c.pf == 1, "half-exchange rows take one tile per workgroup");
-    static_assert(!c.mf || (!c.half && !c.stage && c.pf == 1), "matrix-core rows: full exchange, one tile");
+    static_assert(!c.mf || (!c.half && c.pf == 1), "matrix-core rows: full exchange, one tile");
     static_assert((SPLIT != 0) == (c.mf != 0), "split form of a matrix-core variant");
     if constexpr (c.half && FWD)
         return reinterpret_cast<const void *>(&k_rows_r2c_half<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, EVEN>);
@@ -1981,21 +1981,21 @@ static hipError_t launch_row_from(int idx, const void *in, void *out, const RowR
                 const float *R = static_cast<const float *>(in);
                 float2 *W = static_cast<float2 *>(out);
                 if (a.split == 1) {
-                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 1>), g, t, lds, s, R, W, a, items);
-                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 1>), g, t, lds, s, R, W, a, items);
+                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, c.stage != 0, 1>), g, t, lds, s, R, W, a, items);
+                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, c.stage != 0, 1>), g, t, lds, s, R, W, a, items);
                 } else {
-                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 2>), g, t, lds, s, R, W, a, items);
-                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 2>), g, t, lds, s, R, W, a, items);
+                    if (even) hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, c.stage != 0, 2>), g, t, lds, s, R, W, a, items);
+                    else hipLaunchKernelGGL((k_rows_r2c_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, c.stage != 0, 2>), g, t, lds, s, R, W, a, items);
                 }
             } else {
                 const float2 *W = static_cast<const float2 *>(in);
                 float *S = static_cast<float *>(out);
                 if (a.split == 1) {
-                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 1>), g, t, lds, s, W, S, a, items);
-                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 1>), g, t, lds, s, W, S, a, items);
+                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, c.stage != 0, 1>), g, t, lds, s, W, S, a, items);
+                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, c.stage != 0, 1>), g, t, lds, s, W, S, a, items);
                 } else {
-                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, false, 2>), g, t, lds, s, W, S, a, items);
-                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, false, 2>), g, t, lds, s, W, S, a, items);
+                    if (even) hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, true, c.stage != 0, 2>), g, t, lds, s, W, S, a, items);
+                    else hipLaunchKernelGGL((k_rows_c2r_reg<c.m, c.tf, c.r0, c.r1, c.r2, c.b, c.occ, 1, false, c.stage != 0, 2>), g, t, lds, s, W, S, a, items);
                 }
             }
         } else if (fwd) {

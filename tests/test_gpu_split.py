@@ -116,21 +116,26 @@ def test_split_matrix_core_rows(lp, torch, case, mode):
     G = (rng.random((ny, nx)) - 0.5).astype(np.float32)
     plan = lp.make_plan(K, ny, nx, precision=mode)
     assert plan.padding[1] == 18432 and plan.kernels == lp.KERNELS_SPECIALISED
-    for stage in (lp.STAGE_ROWS, lp.STAGE_ROWS_INVERSE):
-        info = plan.variant_info(stage, plan.variant(stage))
-        assert info["matrix_core"] and info["radices"][0] == 16, info
     x = torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda()
-    S = plan.convolve(x).cpu().numpy()
-    A = plan.adjoint(torch.from_numpy(G).cuda()).cpu().numpy()
-    ref = oracle.conv_same(R, K)
-    e2, em = errors(S, ref, f"matrix-core rows {mode} {case[:4]}")
-    assert e2 <= TOL and em <= TOL
-    a2, am = errors(A, oracle.adjoint_same(G, K), f"matrix-core rows {mode} {case[:4]} adjoint")
-    assert a2 <= TOL and am <= TOL
-    # and at the FP32 path's error level
+    g = torch.from_numpy(G).cuda()
+    ref, aref = oracle.conv_same(R, K), oracle.adjoint_same(G, K)
     S32, _ = run(lp, torch, R, K, None, 0)
     e32, m32 = errors(S32, ref, f"fp32 {case[:4]}")
-    assert e2 <= max(3 * e32, 1e-6) and em <= max(3 * m32, 1e-6)
+    n = plan.variant_count(lp.STAGE_ROWS)
+    assert n >= 2  # with and without the staged intermediate
+    for k in range(n):
+        plan.set_variant(lp.STAGE_ROWS, k)  # both row stages
+        for stage in (lp.STAGE_ROWS, lp.STAGE_ROWS_INVERSE):
+            info = plan.variant_info(stage, plan.variant(stage))
+            assert info["matrix_core"] and info["radices"][0] == 16, info
+        S = plan.convolve(x).cpu().numpy()
+        A = plan.adjoint(g).cpu().numpy()
+        e2, em = errors(S, ref, f"matrix-core rows {mode} {case[:4]} variant {k}")
+        assert e2 <= TOL and em <= TOL
+        a2, am = errors(A, aref, f"matrix-core rows {mode} {case[:4]} variant {k} adjoint")
+        assert a2 <= TOL and am <= TOL
+        # and at the FP32 path's error level
+        assert e2 <= max(3 * e32, 1e-6) and em <= max(3 * m32, 1e-6)
 
 
 # maps whose padded columns are 18432 long: the split forms run register-

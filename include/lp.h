@@ -455,11 +455,10 @@ int lp_batch_tile_group(const lp_batch *batch, int t);
 
 /* Per-class kernel variants, as lp_plan_set_variant: LP_STAGE_ROWS selects
  * the variant of both row stages, LP_STAGE_ROWS_INVERSE the inverse row
- * stage alone, LP_STAGE_COLUMNS the column stage.  A batch keeps a plain
- * column-major intermediate, so its row variants are numbered among those
- * that run on it (the plan variants that stage the two-column interleave
- * are left out; lp_batch_group_info counts the same set).  Invalidates the
- * graph.  Errors: LP_E_INVALID (class, stage or variant out of range). */
+ * stage alone, LP_STAGE_COLUMNS the column stage.  A batch computes in
+ * FP32, so its variants are numbered among the plan variants without a
+ * matrix-core pass (lp_batch_group_info counts the same set).  Invalidates
+ * the graph.  Errors: LP_E_INVALID (class, stage or variant out of range). */
 int lp_batch_set_variant(lp_batch *batch, int g, int stage, int k);
 int lp_batch_get_variant(const lp_batch *batch, int g, int stage);
 

@@ -1303,15 +1303,20 @@ std::vector<int64_t> spec_lengths(bool columns)
     return v;
 }
 
-// A batch keeps a plain column-major intermediate (one column after
-// another) and computes in FP32, so its row variants are those that neither
-// stage the two-column interleave of single-map plans nor run a matrix-core
-// pass: variant k of a batch is the k-th of them.
+// log2 of the column interleave of a batch's intermediates and spectra, and
+// the columns (h, rounded up to whole interleave blocks) each one stores
+constexpr int kBatchLogC = 1;
+int64_t batch_cols(int64_t h) { return ((h + (1 << kBatchLogC) - 1) >> kBatchLogC) << kBatchLogC; }
+
+// A batch keeps each map's intermediate and spectra in the two-column
+// interleave of single-map plans (element i of column v at ((v / 2) ny + i) 2
+// + v mod 2) and computes in FP32, so its row variants are those without a
+// matrix-core pass: variant k of a batch is the k-th of them.
 int batch_row_spec(int64_t m, int k)
 {
     for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i) {
         const int idx = lp::row_spec_index(static_cast<int>(m), i);
-        if (lp::kRowSpecs[idx].stage == 0 && lp::kRowSpecs[idx].mf == 0 && k-- == 0) return idx;
+        if (lp::kRowSpecs[idx].mf == 0 && k-- == 0) return idx;
     }
     return -1;
 }
@@ -1337,10 +1342,8 @@ int batch_col_count(int64_t py)
 int batch_row_count(int64_t m)
 {
     int c = 0;
-    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i) {
-        const lp::RowSpec &r = lp::kRowSpecs[lp::row_spec_index(static_cast<int>(m), i)];
-        c += r.stage == 0 && r.mf == 0;
-    }
+    for (int i = 0, n = lp::row_spec_count(static_cast<int>(m)); i < n; ++i)
+        c += lp::kRowSpecs[lp::row_spec_index(static_cast<int>(m), i)].mf == 0;
     return c;
 }
 
@@ -1399,6 +1402,7 @@ hipError_t batch_launch_all(lp_batch *b, const hipStream_t *streams, int nstream
         lp::RowRegArgs rr{};
         rr.ny = static_cast<int32_t>(g.max_ny);
         rr.nx = g.odd_nx ? 1 : 2;
+        rr.lc = kBatchLogC;
         rr.rtw = reinterpret_cast<const float2 *>(b->ws + g.off_rtw);
         rr.tw_f1 = twr + g.twr_off[0];
         rr.tw_f2 = twr + g.twr_off[1];
@@ -1406,6 +1410,7 @@ hipError_t batch_launch_all(lp_batch *b, const hipStream_t *streams, int nstream
         rr.tw_i2 = twr + g.twr_off[3];
         lp::ColRegArgs cr{};
         cr.ny = 0;
+        cr.lc = kBatchLogC;
         cr.tw_f1 = twc + g.twc_off[0];
         cr.tw_f2 = twc + g.twc_off[1];
         cr.tw_i1 = twc + g.twc_off[2];
@@ -1530,7 +1535,8 @@ static int batch_plan(lp_batch *b)
     for (int t = 0; t < n_tiles; ++t) {
         const lp_batch::Group &g = b->groups[b->item_group[t]];
         b->off_w[t] = off;
-        off += align256(static_cast<size_t>(g.h) * ny[t] * 8);
+        // two interleaved columns (one pad column when h is odd)
+        off += align256(static_cast<size_t>(batch_cols(g.h)) * ny[t] * 8);
     }
     wtotal = off;
     b->w_bytes = wtotal;
@@ -1546,7 +1552,7 @@ static int batch_plan(lp_batch *b)
         g.form.assign(g.psfs.size(), LP_FORM_NONE);
         for (size_t j = 0; j < g.psfs.size(); ++j) {
             g.off_kh.push_back(off);
-            off += align256(static_cast<size_t>(g.py) * g.h * 8);
+            off += align256(static_cast<size_t>(g.py) * batch_cols(g.h) * 8);
         }
         g.off_twc = off;
         off += align256(g.twc_max * 4);
@@ -1735,7 +1741,8 @@ int lp_batch_kernel_spectra(lp_batch *b, const double *const *psfs)
             const double scale = 1.0 / (static_cast<double>(g.py) * static_cast<double>(g.px));
             const int form = sym ? LP_FORM_REAL_QUADRANT : LP_FORM_COMPLEX;
             if ((e = lp::launch_spec_cols(dT1, static_cast<int>(ky), static_cast<int>((ky - 1) / 2), static_cast<int>(g.py),
-                                          ku, static_cast<int>(g.h), 0, static_cast<int>(g.h), dTaby, scale, form,
+                                          ku, static_cast<int>(g.h), kBatchLogC,
+                                          static_cast<int>(batch_cols(g.h) >> kBatchLogC), dTaby, scale, form,
                                           b->ws + g.off_kh[j], b->stream)) != hipSuccess)
                 return fail_hip(e, "spectrum columns launch");
             // the scratch is reused by the next kernel: wait for this one

@@ -204,7 +204,7 @@ struct ColRegArgs {
     int32_t ny;          // stored rows per column
     int32_t ku;          // stored spectrum rows per column (n or n/2+1)
     int32_t lc;          // log2 of the column interleave C of the intermediate and spectrum
-    const void *kh;      // column-major spectrum (float real quadrant or float2)
+    const void *kh;      // spectrum, C = 2^lc interleaved columns (float real quadrant or float2)
     int32_t classes;     // source classes summed before the inverse (class-sum kernels)
     int64_t w_stride;    // float2 elements from one class's intermediate to the next
     int64_t kh_stride;   // bytes from one class's spectrum to the next
@@ -225,7 +225,7 @@ struct ColRegArgs {
 struct BatchItem {
     const float *in;   // radiance, ny x nx
     float *out;        // output rows keep0 .. keep1-1 of the map, nx wide
-    float2 *w;         // intermediate, column-major, (Px/2+1) columns of ny
+    float2 *w;         // intermediate: (Px/2+1) columns of ny, two interleaved
     const void *kh;    // spectrum of the item's kernel at this padded size
     int32_t ny, nx;
     int32_t keep0, keep1;  // output rows [keep0, keep1) of the map, written from out[0]
@@ -317,9 +317,8 @@ constexpr RowSpec kRowSpecs[] = {
     {1800, 180, 12, 10, 15, 2, 0, 1},
     {2160, 180, 12, 12, 15, 2, 0, 1},
     // four and eight rows per workgroup for the shorter rows of batched tiles
-    // and mid-size maps: 32- to 128-byte runs of the intermediate (staged:
-    // the two-column interleave of single-map plans; plain: the column-major
-    // intermediate of batches)
+    // and mid-size maps: 32- to 128-byte runs of the two-column interleave
+    // (staged: through LDS in 16-byte chunks; plain: straight from registers)
     {600, 64, 12, 10, 5, 4, 0, 1, 0, 1},
     {600, 64, 12, 10, 5, 4, 0, 1},
     {600, 64, 12, 10, 5, 8, 0, 1, 0, 1},

@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     using I0 = RegPass<N, R2, 1, TF, 1, 0>;
     using I1 = RegPass<N, R1, R2, TF, 1, R2, JM>;
     using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0, JM>;
-    const int tt = threadIdx.x;
+    const int tt0 = threadIdx.x, tt = tt0;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
     int ny = a.ny;
@@ -492,6 +492,10 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
     // forward transform of one column and product with one spectrum, left in
     // x2 in the order the inverse's first pass takes it
     auto forward = [&](const float2 *srcp, const void *kh, float2 (&x2)[F2::S][R2]) {
+        // a class sum re-reads the thread index per call, so that it does not
+        // keep per-thread addresses and table offsets live across its class
+        // loop
+        const int tt = SUM ? opaque_v(tt0) : tt0;
         const lp_rsrc src = buffer_rsrc(srcp, colb);
         float2 x0[F0::S][R0];
         if constexpr (MF != 0) {
@@ -662,7 +666,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
     using I0 = RegPass<N, R2, 1, TF, 1, 0>;
     using I1 = RegPass<N, R1, R2, TF, 1, R2, JM>;
     using I2 = RegPass<N, R0, R2 * R1, TF, 1, 0, JM>;
-    const int tt = threadIdx.x;
+    const int tt0 = threadIdx.x, tt = tt0;
     const bool act = tt < TF;
     const int v = xcd_tile(blockIdx.x, gridDim.x);
     int ny = a.ny;
@@ -683,7 +687,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 
     // Eq. 9: product of the last forward pass's outputs (element u = i + j NB)
     // with the kernel spectrum
-    auto multiply = [&](float2 (&xl)[F2::S][R2], const void *kh) {
+    auto multiply = [&](float2 (&xl)[F2::S][R2], const void *kh, int tt) {
 #pragma unroll
         for (int s = 0; s < F2::S; ++s) {
             const int i = tt + s * TF;
@@ -712,6 +716,10 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
     };
 
     auto forward = [&](const float2 *srcp, const void *kh, float2 (&xl)[F2::S][R2]) {
+        // a class sum re-reads the thread index per call, so that it does not
+        // keep per-thread addresses and table offsets live across its class
+        // loop
+        const int tt = SUM ? opaque_v(tt0) : tt0;
         const lp_rsrc src = buffer_rsrc(srcp, colb);
         float2 x0[F0::S][R0];
         if (act) {
@@ -744,7 +752,7 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
             F2::template load_part<1>(xl, f, tt, 0);
             F2::template twiddle<false>(xl, buffer_rsrc(a.tw_f2, F2::TABLE_BYTES), tt);
             F2::template butterfly<false>(xl, tt);
-            multiply(xl, kh);
+            multiply(xl, kh, tt);
         }
     };
 

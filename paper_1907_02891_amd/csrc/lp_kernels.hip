@@ -446,8 +446,9 @@ constexpr int MF_AHEAD_HBM = 8;
 // One column per workgroup: forward transform (radices R0, R1, R2), spectrum
 // multiply in registers, inverse transform (radices R2, R1, R0; its first
 // pass consumes the forward's last-pass outputs straight from registers), and
-// only rows < ny read or written.  Column-major intermediate: column v is the
-// contiguous run W[v * ny .. v * ny + ny).
+// only rows < ny read or written.  Intermediate in the column interleave
+// C = 2^lc: element i of column v at ((v / C) ny + i) C + v mod C; the result
+// goes to the same place in a.wout when it is given (out of place).
 // SUM (several source classes, Eq. 4): the forward transform and the product
 // with the class's spectrum are repeated for each class t (intermediate
 // W + t w_stride, spectrum kh + t kh_stride bytes) and summed in registers
@@ -1166,8 +1167,11 @@ __device__ __forceinline__ float2 c2r_merge(float2 x, float2 xp, float2 w)
 // Forward rows.  Passes R0, R1 in the usual thread mapping; the last pass
 // (radix R2, NB = M/R2 butterflies) gives thread tt the butterflies tt and
 // NB - tt, so that it holds both Z[k] and Z[M-k] for every k it produced and
-// the real-to-complex split happens in registers.  Column-major output:
-// X[k] of row r at W[k * ny + r].
+// the real-to-complex split happens in registers.  Output in the column
+// interleave C = 2^lc: X[k] of row r at ((k / C) ny + r) C + k mod C (STG:
+// through LDS, in 16-byte chunks of a column pair).  MF (1 or 2): the
+// radix-16 first pass (R0 = 16) runs on the matrix cores in that split form,
+// reading the rows straight from HBM.
 // TPW tiles of B rows per workgroup, g and g + G (G = grid size); with two,
 // the second tile's inputs are loaded into registers before the first is
 // transformed, so its HBM reads overlap the arithmetic.  The code is straight
@@ -1380,7 +1384,9 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_r2c_reg(const float *__res
 // Inverse rows: the first pass (radix R2, NB = M/R2) pairs butterflies tt and
 // NB - tt so that X[k] and X[M-k] are merged in registers; then passes R1
 // and R0; row outputs x[2n], x[2n+1] for columns < nx (the crop).  TPW tiles
-// per workgroup as in the forward kernel.
+// per workgroup as in the forward kernel.  MF (1 or 2): the radix-16 last
+// pass (R0 = 16) runs on the matrix cores in that split form and writes the
+// rows straight to HBM.
 template <int M, int TF, int R0, int R1, int R2, int B, int OCC, int TPW, bool EVEN_NX, bool STG = false, int MF = 0>
 __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__restrict__ W,
                                                              float *__restrict__ Sm, RowRegArgs a,

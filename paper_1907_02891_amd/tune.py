@@ -26,9 +26,12 @@ def cache_path():
 
 
 def plan_key(plan):
+    """Cache key: shape, padding, spectrum form, classes and precision (a
+    split-precision plan numbers its variants among the matrix-core ones)."""
     py, px = plan.padding
     cls = f"/classes{plan.classes}" if plan.classes > 1 else ""
-    return f"{plan.ny}x{plan.nx}/k{plan.ky}x{plan.kx}/p{py}x{px}/form{plan.form}{cls}"
+    prec = f"/precision{plan.precision}" if plan.precision else ""
+    return f"{plan.ny}x{plan.nx}/k{plan.ky}x{plan.kx}/p{py}x{px}/form{plan.form}{cls}{prec}"
 
 
 def _load_cache():

@@ -246,6 +246,18 @@ def test_python_binding_rejects_host_and_mismatched_tensors():
         p.bind(workspace=torch.zeros(p.workspace_bytes + 256, dtype=torch.uint8))
 
 
+def test_tune_cache_key_separates_precisions():
+    """A split-precision plan numbers its variants among the matrix-core
+    ones, so the autotuner's cache keeps its choices apart from FP32's."""
+    from paper_1907_02891_amd import tune
+    p = lp.Plan(16384, 16384, 2001, 2001)
+    keys = set()
+    for mode in (lp.PRECISION_FP32, lp.PRECISION_SPLIT_FP16, lp.PRECISION_SPLIT_BF16):
+        p.set_precision(mode)
+        keys.add(tune.plan_key(p))
+    assert len(keys) == 3
+
+
 def test_precision_modes_host_side():
     lib = lp.raw()
     p = lp.Plan(16384, 16384, 2001, 2001)

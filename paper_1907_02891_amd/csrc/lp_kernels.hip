@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
                 static_cast<const u4v_t *>(a.mf),
                 [&](int i, int j) {
                     const int n = i + j * F0::NB;
-                    return (n < ny) ? bload2(src, static_cast<unsigned>(n << lc) * 8u) : make_float2(0.f, 0.f);
+                    return bload2(src, static_cast<unsigned>(n << lc) * 8u);  // rows >= ny read zero
                 },
                 [&](int i, int k, float2 v) { lds[i * lds_pitch(16) + k] = v; });
         } else if (act) {
@@ -517,8 +517,8 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                     for (int j = 0; j < R0; ++j) {
                         const int n = i + j * F0::NB;
-                        if (n < ny) x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
-                        else x0[s][j] = make_float2(0.f, 0.f);
+                        // rows >= ny lie past the resource's range: they read zero
+                        x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
                     }
                 }
             }
@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
             },
             [&](int i, int k, float2 v) {
                 const int n = i + k * I2::NB;
-                if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, v);
+                bstore2(col, static_cast<unsigned>(n << lc) * 8u, v);  // rows >= ny: dropped
             });
     } else if (act) {
         float2 y2[I2::S][R0];
@@ -627,7 +627,8 @@ __global__ void __launch_bounds__(((TF + 63) / 64) * 64, SUM ? 0 : OCC) k_cols_r
 #pragma unroll
                 for (int j = 0; j < R0; ++j) {
                     const int n = i + j * I2::NB;
-                    if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, y2[s][j]);
+                    // rows >= ny lie past the resource's range: the store is dropped
+                    bstore2(col, static_cast<unsigned>(n << lc) * 8u, y2[s][j]);
                 }
             }
         }
@@ -731,8 +732,8 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 #pragma unroll
                     for (int j = 0; j < R0; ++j) {
                         const int n = i + j * F0::NB;
-                        if (n < ny) x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
-                        else x0[s][j] = make_float2(0.f, 0.f);
+                        // rows >= ny lie past the resource's range: they read zero
+                        x0[s][j] = bload2(src, static_cast<unsigned>(n << lc) * 8u);
                     }
                 }
             }
@@ -766,7 +767,8 @@ k_cols_half(float2 *__restrict__ W, ColRegArgs a, const BatchItem *__restrict__ 
 #pragma unroll
                 for (int j = 0; j < R0; ++j) {
                     const int n = i + j * I2::NB;
-                    if (n < ny) bstore2(col, static_cast<unsigned>(n << lc) * 8u, y[s][j]);
+                    // rows >= ny lie past the resource's range: the store is dropped
+                    bstore2(col, static_cast<unsigned>(n << lc) * 8u, y[s][j]);
                 }
             }
         }

@@ -43,6 +43,19 @@ __device__ __forceinline__ void gstore2(gptr<T> p, float2 x)
     const lp_f2v v = {x.x, x.y};
     *(gptr<lp_f2v>)p = v;
 }
+// streaming (non-temporal) forms, for data a kernel touches once
+template <class T>
+__device__ __forceinline__ void gstore2_nt(gptr<T> p, float2 x)
+{
+    const lp_f2v v = {x.x, x.y};
+    __builtin_nontemporal_store(v, (gptr<lp_f2v>)p);
+}
+template <class T>
+__device__ __forceinline__ float2 gload2_nt(gptr<const T> p)
+{
+    const lp_f2v v = __builtin_nontemporal_load((gptr<const lp_f2v>)p);
+    return make_float2(v.x, v.y);
+}
 
 // Buffer resources: a base address and a size in bytes held in scalar
 // registers, so that each access needs only a 32-bit per-lane byte offset

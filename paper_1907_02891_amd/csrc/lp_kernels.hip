@@ -1143,7 +1143,7 @@ __device__ __forceinline__ float2 load_pair(gptr<const float> src, int n, int nx
 {
     const int c0 = 2 * n;
     if (!rv || c0 >= nx) return make_float2(0.f, 0.f);
-    if (EVEN_NX) return gload2(src + c0);
+    if (EVEN_NX) return gload2_nt(src + c0);  // read once: a streaming load
     return make_float2(src[c0], (c0 + 1 < nx) ? src[c0 + 1] : 0.f);
 }
 
@@ -1539,7 +1539,7 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
                         const gptr<float> dst = as_global(Sm) + static_cast<int64_t>(r - a.keep0) * a.nx;
                         const int c0 = 2 * (i + k * I2::NB);
                         if (EVEN_NX) {
-                            if (c0 < a.nx) gstore2(dst + c0, v);
+                            if (c0 < a.nx) gstore2_nt(dst + c0, v);
                         } else {
                             if (c0 < a.nx) dst[c0] = v.x;
                             if (c0 + 1 < a.nx) dst[c0 + 1] = v.y;
@@ -1562,7 +1562,8 @@ __global__ void __launch_bounds__(TF * B, OCC) k_rows_c2r_reg(const float2 *__re
                     for (int j = 0; j < R0; ++j) {
                         const int c0 = 2 * (i + j * I2::NB);
                         if (EVEN_NX) {
-                            if (c0 < a.nx) gstore2(dst + c0, y2[s][j]);
+                            // the map is written once: a streaming store
+                            if (c0 < a.nx) gstore2_nt(dst + c0, y2[s][j]);
                         } else {
                             if (c0 < a.nx) dst[c0] = y2[s][j].x;
                             if (c0 + 1 < a.nx) dst[c0 + 1] = y2[s][j].y;

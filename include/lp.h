@@ -296,10 +296,9 @@ int lp_plan_column_split(const lp_plan *plan, int64_t *p1, int64_t *p2);
 
 /* Arithmetic of the transforms (the DFTs of Eq. 10 inside Eq. 9).
  * LP_PRECISION_FP32 (default): every butterfly on the vector ALU in FP32.
- * The split forms factor each transform length with as many radix-16 passes
- * as its power of two allows and run those passes as dense 32 x 32 real
- * matrix products on the matrix cores (v_mfma_f32_16x16x32, FP32
- * accumulation), with both operands split into low-precision terms:
+ * The split forms run radix-16 passes as dense 32 x 32 real matrix products
+ * on the matrix cores (v_mfma_f32_16x16x32, FP32 accumulation), with both
+ * operands split into low-precision terms:
  *   LP_PRECISION_SPLIT_FP16: x = hi + lo in FP16 after scaling each
  *     butterfly's 16 inputs by a power of two (largest in [2^14, 2^15)), the
  *     matrix by 2^14; three products hi*hi + hi*lo + lo*hi;
